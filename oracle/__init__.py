@@ -1,0 +1,181 @@
+"""Serial CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+may import this package.  The product library never loads it, and it shares
+no code with the HIP path: ``oracle.c`` is plain serial C built with gcc,
+and this module only marshals numpy arrays into it.
+
+Functions and the definitions they follow (see ``oracle.c`` for the full
+statement of each):
+
+* :func:`bal`, :func:`iteration_map`, :func:`thread_chunks` -- OpenMP
+  static ``distribute`` / ``for`` schedules (paper sec. 1: the device runtime
+  supplies the routines behind compiler-lowered worksharing loops; sec. 3.1:
+  one team is one GPU thread block).
+* :func:`reduce_int`, :func:`reduce_fp` -- ``reduction(op:x)`` results:
+  integer wrap arithmetic, FP64 Neumaier sums, fmax/fmin folds.
+* :func:`axpy_sum` -- the AXPY worksharing body with fused fmaf.
+* :func:`mlp_loss_grad`, :func:`adam` -- the learned-configuration
+  extension's network in FP64 (not from the paper).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SUM, MAX, MIN = 0, 1, 2
+_OPS = {"sum": SUM, "max": MAX, "min": MIN}
+_FP_DT = {np.dtype(np.float32): 0, np.dtype(np.float64): 1}
+
+_lib = None
+
+
+def build() -> str:
+    """Compile oracle.c with gcc -O2 (no fast-math, single thread)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC",
+           "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    i64, i32, p = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    lib.oracle_bal.argtypes = [i64, i64, i64, p, p]
+    lib.oracle_bal.restype = None
+    lib.oracle_map.argtypes = [i64, i64, i64, i64, i64, p, p]
+    lib.oracle_map.restype = ctypes.c_int
+    lib.oracle_thread_chunks.argtypes = [i64, i64, i64, i64, i64, i64, i64, p, p, i64]
+    lib.oracle_thread_chunks.restype = i64
+    lib.oracle_reduce_i32.argtypes = [p, i64, ctypes.c_int, i32]
+    lib.oracle_reduce_i32.restype = i32
+    lib.oracle_reduce_i64.argtypes = [p, i64, ctypes.c_int, i64]
+    lib.oracle_reduce_i64.restype = i64
+    lib.oracle_reduce_fp.argtypes = [p, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, p]
+    lib.oracle_reduce_fp.restype = ctypes.c_double
+    lib.oracle_axpy_sum.argtypes = [ctypes.c_float, p, p, i64, ctypes.c_double]
+    lib.oracle_axpy_sum.restype = ctypes.c_double
+    lib.oracle_mlp_loss_grad.argtypes = [p, p, i64, i64, i64, i64, i64] + [p] * 13
+    lib.oracle_mlp_loss_grad.restype = ctypes.c_double
+    lib.oracle_adam.argtypes = [p, p, p, p, i64, i64] + [ctypes.c_double] * 4
+    lib.oracle_adam.restype = None
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def bal(m: int, p: int, t: int) -> tuple[int, int]:
+    """Balanced share [lo, hi) of worker t when m iterations go to p workers."""
+    lo, hi = ctypes.c_int64(), ctypes.c_int64()
+    _load().oracle_bal(m, p, t, ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def iteration_map(n: int, teams: int, threads: int, dist_chunk: int = 0,
+                  chunk: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """(owner, count) arrays of the static schedule: owner[i] = team*P+thread."""
+    owner = np.full(n, -1, dtype=np.int32)
+    count = np.zeros(n, dtype=np.uint32)
+    rc = _load().oracle_map(n, teams, threads, dist_chunk, chunk, _ptr(owner), _ptr(count))
+    if rc != 0:
+        raise ValueError("invalid schedule arguments")
+    return owner, count
+
+
+def thread_chunks(n: int, teams: int, threads: int, dist_chunk: int, chunk: int,
+                  team: int, thread: int) -> list[tuple[int, int]]:
+    """The non-empty chunks [lo, hi) thread `thread` of team `team` executes, in order."""
+    lib = _load()
+    cnt = lib.oracle_thread_chunks(n, teams, threads, dist_chunk, chunk, team, thread,
+                                   None, None, 0)
+    lo = np.zeros(max(cnt, 1), dtype=np.int64)
+    hi = np.zeros(max(cnt, 1), dtype=np.int64)
+    lib.oracle_thread_chunks(n, teams, threads, dist_chunk, chunk, team, thread,
+                             _ptr(lo), _ptr(hi), cnt)
+    return [(int(lo[i]), int(hi[i])) for i in range(cnt)]
+
+
+def reduce_int(a: np.ndarray, op: str, x: int = 0) -> int:
+    """x (op) fold(op, a) for int32/int64 arrays, with two's-complement wrap."""
+    a = np.ascontiguousarray(a)
+    lib = _load()
+    if a.dtype == np.int32:
+        return int(lib.oracle_reduce_i32(_ptr(a), a.size, _OPS[op], int(np.int32(x))))
+    if a.dtype == np.int64:
+        return int(lib.oracle_reduce_i64(_ptr(a), a.size, _OPS[op], int(np.int64(x))))
+    raise TypeError(a.dtype)
+
+
+def reduce_fp(a: np.ndarray, op: str, x: float = 0.0, bf16: bool = False,
+              want_abs: bool = False):
+    """x (op) fold(op, a) in FP64 (Neumaier for sums, fmax/fmin otherwise).
+
+    ``a`` is float32 or float64, or uint16 holding bfloat16 bits when
+    ``bf16`` is set.  With ``want_abs`` also returns sum |a_i|.
+    """
+    a = np.ascontiguousarray(a)
+    if bf16:
+        if a.dtype != np.uint16:
+            raise TypeError("bf16 data must be passed as uint16 bits")
+        dt = 2
+    else:
+        dt = _FP_DT[a.dtype]
+    s_abs = ctypes.c_double()
+    r = _load().oracle_reduce_fp(_ptr(a), a.size, dt, _OPS[op], float(x),
+                                 ctypes.byref(s_abs) if want_abs else None)
+    return (r, s_abs.value) if want_abs else r
+
+
+def axpy_sum(a: float, x: np.ndarray, y: np.ndarray, s_orig: float = 0.0):
+    """Returns (y_new, sum) with y_new[i] = fmaf(a, x[i], y[i]); y is not modified."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y2 = np.array(y, dtype=np.float32, copy=True)
+    s = _load().oracle_axpy_sum(ctypes.c_float(a), _ptr(x), _ptr(y2), x.size, float(s_orig))
+    return y2, s
+
+
+def mlp_loss_grad(X, y, params, want_grad=True):
+    """Mean softmax-CE loss (and FP64 gradients) of the F->H1->H2->K ReLU MLP.
+
+    ``params`` = dict with W1[H1,F], b1[H1], W2[H2,H1], b2[H2], W3[K,H2], b3[K].
+    Returns (loss, logits, grads-dict or None).
+    """
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    P = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in params.items()}
+    B, F = X.shape
+    H1, H2, K = P["W1"].shape[0], P["W2"].shape[0], P["W3"].shape[0]
+    Z = np.zeros((B, K))
+    g = {k: np.zeros_like(v) for k, v in P.items()} if want_grad else None
+    gp = [_ptr(g[k]) for k in ("W1", "b1", "W2", "b2", "W3", "b3")] if want_grad else [None] * 6
+    loss = _load().oracle_mlp_loss_grad(
+        _ptr(X), _ptr(y), B, F, H1, H2, K,
+        _ptr(P["W1"]), _ptr(P["b1"]), _ptr(P["W2"]), _ptr(P["b2"]),
+        _ptr(P["W3"]), _ptr(P["b3"]), _ptr(Z), *gp)
+    return loss, Z, g
+
+
+def adam(w, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One FP64 Adam step at step number t >= 1; returns new (w, m, v)."""
+    w = np.array(w, dtype=np.float64, copy=True)
+    m = np.array(m, dtype=np.float64, copy=True)
+    v = np.array(v, dtype=np.float64, copy=True)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    _load().oracle_adam(_ptr(w), _ptr(m), _ptr(v), _ptr(g), w.size, t, lr, beta1, beta2, eps)
+    return w, m, v
