@@ -1,0 +1,153 @@
+"""Benchmark of the data-parallel reduction core on one MI355X.
+
+One step = one pass of the plain reduction path over the at-scale
+workload: fp32 sum and fp32 max over N = 2^28 elements ~ N(0, 1) and int64
+sum over N = 2^28 elements uniform in [-2^40, 2^40] (4 GiB read per step),
+inputs resident in HBM, launch configuration chosen by the runtime.  The
+printed JSON line reports whole-step throughput in GB/s, the roofline of the
+dominant kernel (the int64 sum, timed with HIP events on its stream over
+the timed region), and the CPU oracle timed on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N = 1 << 28
+METRIC = "reduction GB/s (% HBM peak); batched reductions/s learned vs plain at 1e-6"
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(f_host, i_host, passes: int):
+    """The oracle, as is, over the same workload on one host core."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        oracle.reduce_fp(f_host, "sum", 0.0)
+        oracle.reduce_fp(f_host, "max", -np.inf)
+        oracle.reduce_int(i_host, "sum", 0)
+    dt = time.perf_counter() - t0
+    step_bytes = f_host.nbytes * 2 + i_host.nbytes
+    return {"value": round(passes * step_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{passes} serial passes of the full step (fp32 sum, fp32 max, int64 sum "
+                      f"over 2^28 each; {dt:.1f} s), FP64 Neumaier sums"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-passes", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(this build runs and reports single-GPU throughput)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2106_03219_amd as om
+    import synth
+    om.load()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    _log("generating inputs on the device")
+    f = synth.device(synth.F32, N, synth.SEED_F32)
+    i = synth.device(synth.I64, N, synth.SEED_I64)
+    xs = torch.zeros(1, dtype=torch.float32, device="cuda")
+    xm = torch.full((1,), -float("inf"), dtype=torch.float32, device="cuda")
+    xi = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cfg_f, _ = om.resolve_config(N, om.F32, "sum")
+    cfg_i, _ = om.resolve_config(N, om.I64, "sum")
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        om.reduce(i, "sum", xi)
+        if ev is not None:
+            ev[1].record(stream)
+        om.reduce(f, "sum", xs)
+        om.reduce(f, "max", xm)
+
+    # parity of one step against the oracle (outside the timed region)
+    _log("parity check against the oracle")
+    xs.zero_(); xm.fill_(-float("inf")); xi.zero_()
+    step()
+    torch.cuda.synchronize()
+    f_host = f.cpu().numpy()
+    i_host = i.cpu().numpy()
+    import oracle
+    ref_s, abs_s = oracle.reduce_fp(f_host, "sum", 0.0, want_abs=True)
+    ref_m = oracle.reduce_fp(f_host, "max", -np.inf)
+    ref_i = oracle.reduce_int(i_host, "sum", 0)
+    rel = abs(xs.item() - ref_s) / abs(ref_s)
+    parity = {"fp32_sum_rel_err": rel, "fp32_sum_kappa": abs_s / abs(ref_s),
+              "fp32_max_exact": xm.item() == ref_m, "int64_sum_exact": xi.item() == ref_i}
+    if not (rel <= 1e-6 and parity["fp32_max_exact"] and parity["int64_sum_exact"]):
+        _log(f"PARITY FAILURE {parity}")
+        sys.exit(1)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    _log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    step_bytes = f.numel() * 4 * 2 + i.numel() * 8
+    value = args.steps * step_bytes / dt / 1e9
+    kern_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    achieved = i.numel() * 8 / (kern_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "reduce_kernel<int64,sum,16B,unroll>", "avg_launch_us": round(kern_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": i.numel() * 8}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        _log("timing the CPU oracle")
+        cpu = cpu_baseline(f_host, i_host, args.cpu_passes)
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32,i64",
+        "data": "synthetic",
+        "config": {"workload": "plain reductions at scale: fp32 sum + fp32 max over 2^28 N(0,1), "
+                               "int64 sum over 2^28 U[-2^40,2^40]; static team blocks",
+                   "n": N, "bytes_per_step": step_bytes,
+                   "launch_fp32": cfg_f, "launch_int64": cfg_i},
+        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "parity": parity,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

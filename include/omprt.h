@@ -1,0 +1,295 @@
+/*
+ * omprt.h -- C ABI of an MI355X (gfx950) implementation of the data-parallel
+ * core of an OpenMP device runtime: what a
+ *     #pragma omp target teams distribute parallel for reduction(op:x)
+ * region lowers to.  The paper this follows (Tian, Chesterfield, Doerfert,
+ * Chapman, "Experience Report: Writing A Portable GPU Runtime with OpenMP
+ * 5.1") describes the device runtime as the library that supplies OpenMP
+ * semantics on the GPU, including the routines the compiler calls for
+ * worksharing loops (sec. 1, sec. 2.1); it maps one OpenMP team to one GPU
+ * thread block (sec. 3.1, "Global Shared Variables"); team-shared variables
+ * live in on-chip shared memory and are uninitialised until written
+ * (sec. 3.1); cross-thread communication uses device atomics, in particular
+ * a wrap-around increment, and a flush that is a device fence (sec. 3.1
+ * "Atomic Operations", Listing of the flush entry, sec. 3.2).
+ *
+ * Conventions for every entry point:
+ *  - Pointers prefixed d_ are device pointers (hipMalloc / torch CUDA
+ *    tensors); h_ are host pointers.  The caller owns all of them; the
+ *    library never frees or retains a caller buffer beyond the call, except
+ *    that buffers named by a cached batched plan must stay valid until the
+ *    next omprt_reduce_batched call with a different plan, or
+ *    omprt_finalize.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Device work
+ *    is enqueued asynchronously and stream-ordered; no entry point
+ *    synchronises the device unless it says so.  Results are visible after
+ *    the stream is synchronised.
+ *  - Every function returns an omprt_status and never aborts; after a
+ *    non-OK status omprt_last_error() holds a message (per host thread).
+ *    Device faults surface at the caller's next synchronisation.
+ *  - Calls on one stream are serialised by the stream.  Different streams
+ *    get different workspaces, so concurrent calls on different streams do
+ *    not interfere.  Two host threads must not share one stream.
+ */
+#ifndef OMPRT_H
+#define OMPRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OMPRT_OK = 0,
+    OMPRT_ERR_INVALID = 1,      /* bad argument (null pointer, range, ...) */
+    OMPRT_ERR_UNSUPPORTED = 2,  /* valid but not implemented (dtype/op combo) */
+    OMPRT_ERR_NOMEM = 3,        /* workspace allocation failed or over limit */
+    OMPRT_ERR_DEVICE = 4        /* HIP runtime error on launch/copy/capture */
+} omprt_status;
+
+typedef enum {
+    OMPRT_I32 = 0, OMPRT_I64 = 1, OMPRT_F32 = 2, OMPRT_F64 = 3, OMPRT_BF16 = 4
+} omprt_dtype;
+
+typedef enum { OMPRT_SUM = 0, OMPRT_MAX = 1, OMPRT_MIN = 2 } omprt_op;
+
+/*
+ * A static worksharing schedule:
+ *   distribute dist_schedule(static[, dist_chunk]) parallel for
+ *   schedule(static[, chunk])
+ * over logical iterations 0..n-1 with num_teams teams of
+ * threads_per_team threads.  A chunk of 0 means "no chunk size given":
+ *   - dist_chunk == 0: team k executes the balanced block
+ *     [k*q + min(k, r), ... + q + (k < r)) with q = n / T, r = n % T;
+ *   - dist_chunk > 0: blocks [j*dc, min(n, (j+1)*dc)) go to team j mod T;
+ *   - chunk == 0: inside each team block [a, b) (m = b - a) thread t
+ *     executes the balanced share a + bal(m, P, t) (first m % P threads one
+ *     extra iteration);
+ *   - chunk > 0: chunks [a + j*c, a + min(m, (j+1)*c)) go to thread j mod P,
+ *     dealt again from thread 0 in every team block.
+ * Surplus teams/threads (T > n, P > m) execute nothing.
+ */
+typedef struct {
+    int64_t n;                  /* trip count, >= 0 */
+    int32_t num_teams;          /* >= 1 (0 = runtime picks, where allowed) */
+    int32_t threads_per_team;   /* 1..1024 (0 = runtime picks, where allowed) */
+    int64_t dist_chunk;         /* >= 0 */
+    int64_t chunk;              /* >= 0 */
+} omprt_sched;
+
+/*
+ * Launch configuration for reductions.  Zero fields mean "runtime picks":
+ * the learned model if one is loaded (and confident), else the tuned cache,
+ * else a built-in heuristic.
+ */
+typedef struct {
+    int32_t num_teams;          /* 0, or 1..65535 */
+    int32_t threads_per_team;   /* 0, or 64..1024 in steps of 64 */
+    int32_t vec_bytes;          /* 0, 8 or 16: bytes per lane per load */
+    int32_t unroll;             /* 0, 1, 2, 4 or 8 loads in flight per lane */
+    int32_t tile_kib;           /* batched only: tile size in KiB (0, or 4..65536) */
+    uint32_t flags;             /* OMPRT_CFG_* */
+} omprt_config;
+
+#define OMPRT_CFG_NO_MODEL 0x1u      /* ignore the learned model for this call */
+#define OMPRT_CFG_STATIC_TILES 0x2u  /* batched: deal tiles round-robin instead of
+                                        by atomic ticket */
+
+/* One independent reduction of a batch.  x follows omprt_reduce. */
+typedef struct {
+    const void *d_in;
+    int64_t n;
+    int32_t dtype;              /* omprt_dtype */
+    int32_t op;                 /* omprt_op */
+    void *d_x;
+} omprt_segment;
+
+/* ----------------------------------------------------------------------- */
+/* Static worksharing (host)                                               */
+/* ----------------------------------------------------------------------- */
+
+/*
+ * The j-th (0-based) non-empty chunk that thread `thread` of team `team`
+ * executes under schedule *s, as the half-open range [*lb, *ub) of logical
+ * iterations, in execution order.  When j is at or past the thread's last
+ * chunk, *lb == *ub == s->n.  *is_last is 1 when the chunk holds iteration
+ * n-1 (the sequentially last iteration), else 0.  Pure host integer
+ * arithmetic, O(1).  A thread's chunks do not in general form one
+ * arithmetic progression (dist_chunk > 0 and chunk > 0), hence the index.
+ * Errors: INVALID for NULL pointers, n < 0, num_teams < 1,
+ * threads_per_team outside 1..1024, negative chunks, team/thread out of
+ * range, j < 0.
+ */
+omprt_status omprt_for_static_bounds(const omprt_sched *s, int32_t team,
+                                     int32_t thread, int64_t j, int64_t *lb,
+                                     int64_t *ub, int32_t *is_last);
+
+/* Number of non-empty chunks and of iterations thread `thread` of team
+ * `team` executes under *s.  Same errors as omprt_for_static_bounds. */
+omprt_status omprt_sched_count(const omprt_sched *s, int32_t team,
+                               int32_t thread, int64_t *n_chunks,
+                               int64_t *n_iters);
+
+/* ----------------------------------------------------------------------- */
+/* Device work                                                             */
+/* ----------------------------------------------------------------------- */
+
+/*
+ * Iteration map of schedule *s on the GPU: the thread executing iteration i
+ * stores owner[i] = team * threads_per_team + thread and atomically adds 1
+ * to count[i].  d_owner and d_count have s->n entries; the caller zeroes
+ * d_count first (a correct map leaves every count at 1).  num_teams and
+ * threads_per_team must be given (no runtime choice).  Verification
+ * kernel for the schedule semantics.
+ */
+omprt_status omprt_static_map(const omprt_sched *s, int32_t *d_owner,
+                              uint32_t *d_count, void *hip_stream);
+
+/*
+ * reduction(op:x) over d_in[0..n):  *d_x <- *d_x (op) fold(op, d_in[0..n)).
+ * dtype gives d_in's element type.  *d_x has the input's type, except for
+ * bf16 sums, whose *d_x is float (the fp32 accumulator).  Integer sums wrap
+ * modulo 2^w; max/min compare signed (integers) or follow IEEE maxNum /
+ * minNum (floating, NaN-dropping).  fp32 and bf16 sums accumulate in
+ * compensated fp32 (per-lane Kahan, float-float combination); fp64 sums in
+ * fp64.  n == 0 leaves *d_x unchanged.  The result is deterministic for a
+ * fixed (n, configuration).  Teams follow the static distribute schedule
+ * (team k reduces the balanced block bal(n, T, k)); inside a team lanes read
+ * interleaved vectors, which no reduction body can observe.  The cross-team
+ * combine is done by the last team to finish, found with a wrap-around
+ * atomic increment that leaves its counter at 0.
+ * d_in needs only element alignment.  cfg may be NULL.
+ */
+omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
+                          int32_t op, void *d_x, const omprt_config *cfg,
+                          void *hip_stream);
+
+/*
+ * count independent reductions in ONE persistent kernel launch.  h_segs is
+ * a host array; each segment follows omprt_reduce's semantics.  The plan
+ * (descriptor and tile tables) and a captured HIP graph of the launch are
+ * cached per (stream, segment list, configuration): a repeat call with the
+ * same list only replays the graph.  Segments may not alias each other's
+ * outputs.  cfg's threads_per_team / unroll / vec_bytes select the tile
+ * kernel; num_teams the persistent grid size (0 = one full wave of the
+ * device).
+ */
+omprt_status omprt_reduce_batched(const omprt_segment *h_segs, int32_t count,
+                                  const omprt_config *cfg, void *hip_stream);
+
+/*
+ * The same segments as omprt_reduce_batched, as one omprt_reduce launch
+ * each (the plain form, for comparison).  cfg as for omprt_reduce.
+ */
+omprt_status omprt_reduce_each(const omprt_segment *h_segs, int32_t count,
+                               const omprt_config *cfg, void *hip_stream);
+
+/*
+ * Worksharing body with a reduction, under the exact static schedule *s:
+ * every iteration i is executed by the thread the schedule assigns it to,
+ * and does   y[i] <- fmaf(a, x[i], y[i]);  sum += y[i]  (updated value).
+ * On exit *d_sum <- *d_sum + sum (compensated fp32 as in omprt_reduce).
+ * s->num_teams / threads_per_team of 0 let the runtime pick; dist_chunk and
+ * chunk are honoured exactly.  x and y must not overlap.
+ */
+omprt_status omprt_axpy_sum(float a, const float *d_x, float *d_y,
+                            float *d_sum, const omprt_sched *s,
+                            const omprt_config *cfg, void *hip_stream);
+
+/*
+ * An empty target region: one launch of s->num_teams teams in which every
+ * thread computes its static-schedule bounds over s->n iterations and runs
+ * an empty body, then the team barrier.  For launch-latency measurement.
+ */
+omprt_status omprt_empty_region(const omprt_sched *s, void *hip_stream);
+
+/* ----------------------------------------------------------------------- */
+/* Learned launch configuration (extension; not in the paper)              */
+/* ----------------------------------------------------------------------- */
+
+/*
+ * Network: F -> H1 -> H2 -> K, ReLU, fp32, softmax over K configuration
+ * classes.  Parameters live in one contiguous fp32 buffer in the order
+ * W1[H1][F], b1[H1], W2[H2][H1], b2[H2], W3[K][H2], b3[K] (row-major).
+ */
+typedef struct { int32_t F, H1, H2, K; } omprt_mlp_dims;
+
+/* Number of fp32 parameters of a network of these dimensions. */
+int64_t omprt_mlp_param_count(const omprt_mlp_dims *d);
+
+/* Logits d_Z[B][K] of the rows d_X[B][F]. */
+omprt_status omprt_mlp_forward(const omprt_mlp_dims *d, const float *d_params,
+                               const float *d_X, int32_t B, float *d_Z,
+                               void *hip_stream);
+
+/*
+ * Mean softmax cross-entropy of d_X[B][F] against labels d_y[B] in 0..K-1:
+ * writes the loss to d_loss[0] and the gradient with respect to every
+ * parameter to d_grads (same layout as d_params).  ReLU'(0) = 0.
+ * B <= 65536.
+ */
+omprt_status omprt_mlp_loss_grad(const omprt_mlp_dims *d,
+                                 const float *d_params, const float *d_X,
+                                 const int32_t *d_y, int32_t B, float *d_loss,
+                                 float *d_grads, void *hip_stream);
+
+/* One Adam step (Kingma & Ba) at step number `step` >= 1 on n parameters. */
+omprt_status omprt_mlp_adam(float *d_params, float *d_m, float *d_v,
+                            const float *d_grads, int64_t n, int32_t step,
+                            float lr, float beta1, float beta2, float eps,
+                            void *hip_stream);
+
+/*
+ * Load (path != NULL) or unload (path == NULL) the learned picker used when
+ * a reduction's cfg leaves fields at 0.  File format: text, written by the
+ * package's training driver (dims, feature scaling, class table, weights).
+ */
+omprt_status omprt_model_load(const char *path);
+
+/* Features of a call, as the picker sees them (16 floats, host). */
+omprt_status omprt_model_features(int64_t n, int32_t dtype, int32_t op,
+                                  int32_t body, int64_t chunk, float *h_f16);
+
+/*
+ * The configuration the runtime would use for a call with these
+ * properties (body: 0 = plain reduction, 1 = AXPY body; chunk: the user's
+ * chunk, -1 = none).  Fills *out; *source = 0 explicit, 1 learned model,
+ * 2 tuned cache, 3 heuristic.
+ */
+omprt_status omprt_resolve_config(int64_t n, int32_t dtype, int32_t op,
+                                  int32_t body, int64_t chunk,
+                                  const omprt_config *cfg, omprt_config *out,
+                                  int32_t *source);
+
+/* Tuned cache entry: calls whose (dtype, op, body, floor(log2 n)) match use
+ * *cfg when no model decides.  cfg == NULL removes the entry. */
+omprt_status omprt_tune_set(int32_t dtype, int32_t op, int32_t body,
+                            int32_t log2n, const omprt_config *cfg);
+
+/* ----------------------------------------------------------------------- */
+/* Runtime                                                                 */
+/* ----------------------------------------------------------------------- */
+
+/* Allocate the stream's workspace for up to max_teams teams and
+ * max_counters batched counters now (needed before the first call inside a
+ * caller's own graph capture). */
+omprt_status omprt_workspace_reserve(void *hip_stream, int32_t max_teams,
+                                     int32_t max_counters);
+
+/* Re-zero the stream's cross-team counters (after an aborted launch). */
+omprt_status omprt_workspace_reset(void *hip_stream);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *omprt_last_error(void);
+
+/* Library version string. */
+const char *omprt_version(void);
+
+/* Free every workspace, plan and graph.  Synchronises the device. */
+omprt_status omprt_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OMPRT_H */

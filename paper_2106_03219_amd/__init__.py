@@ -1,0 +1,225 @@
+"""omprt -- the data-parallel core of an OpenMP device runtime on MI355X.
+
+Thin Python binding of libomprt.so (include/omprt.h): argument marshalling
+only.  Every step runs in the library's HIP kernels; torch is used for
+device memory and streams.  Functions keep the C names without the
+``omprt_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (BF16, CFG_NO_MODEL, CFG_STATIC_TILES, F32, F64, I32, I64, MAX, MIN, SUM,
+                   Config, MlpDims, OmprtError, Sched, Segment, check)
+
+__all__ = [
+    "load", "version", "for_static_bounds", "sched_count", "static_map", "reduce",
+    "reduce_batched", "reduce_each", "make_segments", "axpy_sum", "empty_region",
+    "mlp_param_count", "mlp_forward", "mlp_loss_grad", "mlp_adam", "model_load",
+    "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
+    "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
+    "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "CFG_NO_MODEL", "CFG_STATIC_TILES",
+]
+
+_OPS = {"sum": SUM, "max": MAX, "min": MIN}
+
+
+def load():
+    """Load the library (raises if it is not built)."""
+    return _lib.load()
+
+
+def version() -> str:
+    return load().omprt_version().decode()
+
+
+def _op(op) -> int:
+    return _OPS[op] if isinstance(op, str) else int(op)
+
+
+def dtype_code(t) -> int:
+    import torch
+    m = {torch.int32: I32, torch.int64: I64, torch.float32: F32, torch.float64: F64,
+         torch.bfloat16: BF16}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def _stream(stream) -> int | None:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream or None
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+def _cfg(config):
+    if config is None:
+        return None
+    if isinstance(config, Config):
+        return ctypes.byref(config)
+    c = Config()
+    c.num_teams = config.get("teams", 0)
+    c.threads_per_team = config.get("threads", 0)
+    c.vec_bytes = config.get("vec", 0)
+    c.unroll = config.get("unroll", 0)
+    c.tile_kib = config.get("tile_kib", 0)
+    c.flags = config.get("flags", 0)
+    return ctypes.byref(c)
+
+
+def _sched(n, teams, threads, dist_chunk=0, chunk=0) -> Sched:
+    return Sched(int(n), int(teams), int(threads), int(dist_chunk), int(chunk))
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    return t.data_ptr() or None
+
+
+# ---------------------------------------------------------------- schedules
+
+def for_static_bounds(n, teams, threads, dist_chunk, chunk, team, thread, j):
+    """(lb, ub, is_last) of the j-th chunk of (team, thread); lb == ub == n past the end."""
+    lb, ub, last = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    s = _sched(n, teams, threads, dist_chunk, chunk)
+    check(load().omprt_for_static_bounds(ctypes.byref(s), team, thread, j, ctypes.byref(lb),
+                                         ctypes.byref(ub), ctypes.byref(last)),
+          "for_static_bounds")
+    return lb.value, ub.value, last.value
+
+
+def sched_count(n, teams, threads, dist_chunk, chunk, team, thread):
+    """(n_chunks, n_iters) of (team, thread)."""
+    c, it = ctypes.c_int64(), ctypes.c_int64()
+    s = _sched(n, teams, threads, dist_chunk, chunk)
+    check(load().omprt_sched_count(ctypes.byref(s), team, thread, ctypes.byref(c),
+                                   ctypes.byref(it)), "sched_count")
+    return c.value, it.value
+
+
+def static_map(n, teams, threads, dist_chunk, chunk, owner, count, stream=None):
+    """GPU iteration map into int32 owner[n] / int32-or-uint32 count[n] (count zeroed by caller)."""
+    s = _sched(n, teams, threads, dist_chunk, chunk)
+    check(load().omprt_static_map(ctypes.byref(s), _ptr(owner), _ptr(count), _stream(stream)),
+          "static_map")
+
+
+def empty_region(n, teams, threads, dist_chunk=0, chunk=0, stream=None):
+    s = _sched(n, teams, threads, dist_chunk, chunk)
+    check(load().omprt_empty_region(ctypes.byref(s), _stream(stream)), "empty_region")
+
+
+# ---------------------------------------------------------------- reductions
+
+def reduce(inp, op, x, config=None, stream=None, n=None):
+    """x <- x (op) fold(op, inp[:n]) on the GPU (inp 1-D contiguous, x one element)."""
+    if not inp.is_contiguous():
+        raise ValueError("input must be contiguous")
+    nn = inp.numel() if n is None else int(n)
+    check(load().omprt_reduce(_ptr(inp) if nn else (inp.data_ptr() or None), nn, dtype_code(inp),
+                              _op(op), _ptr(x), _cfg(config), _stream(stream)), "reduce")
+
+
+def make_segments(items):
+    """ctypes Segment array from [(input tensor, op, x tensor[, n]), ...]."""
+    arr = (Segment * len(items))()
+    for i, it in enumerate(items):
+        inp, op, x = it[0], it[1], it[2]
+        n = it[3] if len(it) > 3 else inp.numel()
+        arr[i] = Segment(inp.data_ptr() or None, int(n), dtype_code(inp), _op(op), x.data_ptr())
+    return arr
+
+
+def reduce_batched(segments, config=None, stream=None):
+    """All segments in one persistent, graph-replayed launch (see make_segments)."""
+    arr = segments if isinstance(segments, ctypes.Array) else make_segments(segments)
+    check(load().omprt_reduce_batched(arr, len(arr), _cfg(config), _stream(stream)),
+          "reduce_batched")
+
+
+def reduce_each(segments, config=None, stream=None):
+    """The same segments as one plain launch each."""
+    arr = segments if isinstance(segments, ctypes.Array) else make_segments(segments)
+    check(load().omprt_reduce_each(arr, len(arr), _cfg(config), _stream(stream)), "reduce_each")
+
+
+def axpy_sum(a, x, y, s, teams=0, threads=0, dist_chunk=0, chunk=0, config=None, stream=None):
+    """y <- fmaf(a, x, y) under the exact static schedule; s[0] += sum(updated y)."""
+    sch = _sched(x.numel(), teams, threads, dist_chunk, chunk)
+    check(load().omprt_axpy_sum(ctypes.c_float(a), _ptr(x) if x.numel() else None,
+                                _ptr(y) if y.numel() else None, _ptr(s), ctypes.byref(sch),
+                                _cfg(config), _stream(stream)), "axpy_sum")
+
+
+# ---------------------------------------------------------------- learned picker
+
+def mlp_param_count(F, H1, H2, K) -> int:
+    d = MlpDims(F, H1, H2, K)
+    return int(load().omprt_mlp_param_count(ctypes.byref(d)))
+
+
+def mlp_forward(dims, params, X, Z, stream=None):
+    d = MlpDims(*dims)
+    check(load().omprt_mlp_forward(ctypes.byref(d), _ptr(params), _ptr(X), X.shape[0], _ptr(Z),
+                                   _stream(stream)), "mlp_forward")
+
+
+def mlp_loss_grad(dims, params, X, y, loss, grads, stream=None):
+    d = MlpDims(*dims)
+    check(load().omprt_mlp_loss_grad(ctypes.byref(d), _ptr(params), _ptr(X), _ptr(y), X.shape[0],
+                                     _ptr(loss), _ptr(grads), _stream(stream)), "mlp_loss_grad")
+
+
+def mlp_adam(params, m, v, grads, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(load().omprt_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grads), params.numel(),
+                                int(step), lr, beta1, beta2, eps, _stream(stream)), "mlp_adam")
+
+
+def model_load(path):
+    """Load (path) or unload (None) the learned configuration picker."""
+    check(load().omprt_model_load(None if path is None else str(path).encode()), "model_load")
+
+
+def model_features(n, dtype, op, body=0, chunk=-1):
+    f = (ctypes.c_float * 16)()
+    check(load().omprt_model_features(int(n), int(dtype), _op(op), int(body), int(chunk), f),
+          "model_features")
+    return list(f)
+
+
+def resolve_config(n, dtype, op, body=0, chunk=-1, config=None):
+    """(dict(teams, threads, vec, unroll), source) with source 0 explicit, 1 model, 2 tuned, 3 heuristic."""
+    out = Config()
+    src = ctypes.c_int32()
+    check(load().omprt_resolve_config(int(n), int(dtype), _op(op), int(body), int(chunk),
+                                      _cfg(config), ctypes.byref(out), ctypes.byref(src)),
+          "resolve_config")
+    return ({"teams": out.num_teams, "threads": out.threads_per_team, "vec": out.vec_bytes,
+             "unroll": out.unroll}, src.value)
+
+
+def tune_set(dtype, op, body, log2n, config):
+    check(load().omprt_tune_set(int(dtype), _op(op), int(body), int(log2n), _cfg(config)),
+          "tune_set")
+
+
+# ---------------------------------------------------------------- runtime
+
+def workspace_reserve(max_teams, max_counters=0, stream=None):
+    check(load().omprt_workspace_reserve(_stream(stream), int(max_teams), int(max_counters)),
+          "workspace_reserve")
+
+
+def workspace_reset(stream=None):
+    check(load().omprt_workspace_reset(_stream(stream)), "workspace_reset")
+
+
+def finalize():
+    check(load().omprt_finalize(), "finalize")

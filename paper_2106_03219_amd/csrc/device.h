@@ -1,0 +1,344 @@
+// device.h -- gfx950 device primitives of the data-parallel core:
+// wave64 cross-lane reduction (DPP + bpermute), the intra-team tree through
+// LDS with the team barrier, the cross-team publish / wrap-increment /
+// last-team protocol, compensated (float-float) arithmetic, and the
+// element-type and reduction-operator policies the kernels are templated on.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sched.h"
+
+namespace omprt {
+
+enum { DT_I32 = 0, DT_I64 = 1, DT_F32 = 2, DT_F64 = 3, DT_BF16 = 4, DT_COUNT = 5 };
+enum { OP_SUM = 0, OP_MAX = 1, OP_MIN = 2, OP_COUNT = 3 };
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kWave = 64;
+constexpr int kMaxWaves = 1024 / kWave;
+
+// ---------------------------------------------------------------- cross-lane
+
+// GFX9 DPP controls used by the wave reduction (all stay inside a row of 16
+// lanes, so every source lane exists when the wave is full).
+enum : int {
+    kDppQuadXor1 = 0xB1,   // quad_perm [1,0,3,2]
+    kDppQuadXor2 = 0x4E,   // quad_perm [2,3,0,1]
+    kDppRowRor4 = 0x124,   // row_ror:4
+    kDppRowRor8 = 0x128,   // row_ror:8
+};
+
+template <int CTRL, class T>
+__device__ __forceinline__ T dpp_move(const T& x) {
+    static_assert(sizeof(T) % 4 == 0, "DPP moves whole dwords");
+    constexpr int W = sizeof(T) / 4;
+    int w[W];
+    __builtin_memcpy(w, &x, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_update_dpp(w[i], w[i], CTRL, 0xF, 0xF, false);
+    T y;
+    __builtin_memcpy(&y, w, sizeof(T));
+    return y;
+}
+
+template <class T>
+__device__ __forceinline__ T shfl_xor_words(const T& x, int mask) {
+    static_assert(sizeof(T) % 4 == 0, "shuffles move whole dwords");
+    constexpr int W = sizeof(T) / 4;
+    int w[W];
+    __builtin_memcpy(w, &x, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = __shfl_xor(w[i], mask, kWave);
+    T y;
+    __builtin_memcpy(&y, w, sizeof(T));
+    return y;
+}
+
+// 64 lane partials -> 1 (every lane ends with a full combination; lane 0's
+// value is the one used).  Must be called with all 64 lanes active.
+template <class R>
+__device__ __forceinline__ typename R::Acc wave_reduce(typename R::Acc a) {
+    a = R::combine(a, dpp_move<kDppQuadXor1>(a));
+    a = R::combine(a, dpp_move<kDppQuadXor2>(a));
+    a = R::combine(a, dpp_move<kDppRowRor4>(a));
+    a = R::combine(a, dpp_move<kDppRowRor8>(a));
+    a = R::combine(a, shfl_xor_words(a, 16));
+    a = R::combine(a, shfl_xor_words(a, 32));
+    return a;
+}
+
+// Intra-team tree: each wave reduces, lane 0 of wave w writes LDS slot w,
+// team barrier, wave 0 reduces the slots.  Slots past the wave count are
+// never read (LDS is not zero-initialised).  Result valid in thread 0.
+// blockDim.x must be a multiple of 64.
+template <class R>
+__device__ __forceinline__ typename R::Acc team_reduce(typename R::Acc a,
+                                                       typename R::Acc* slots) {
+    a = wave_reduce<R>(a);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    if (lane == 0) slots[wave] = a;
+    __syncthreads();
+    if (wave == 0) {
+        a = lane < nw ? slots[lane] : R::identity();
+        a = wave_reduce<R>(a);
+    }
+    return a;
+}
+
+// Cross-team step.  Thread 0 stores the team's partial to its slot, then
+// performs the wrap-around increment  { v = *ctr; *ctr = v >= e ? 0 : v+1 }
+// with acquire-release ordering at agent scope (the release makes the slot
+// store visible before the increment; the device-wide fence behind the
+// OpenMP flush).  With e = participants - 1 exactly one team reads e: it is
+// the last, and it leaves the counter at 0 for the next launch or replay.
+// Returns the same bool in every thread of the team; the last team has also
+// executed an agent-scope acquire fence, so every partial is visible to it.
+template <class Acc>
+__device__ __forceinline__ bool publish_and_is_last(const Acc& partial, Acc* slot,
+                                                    uint32_t* counter, uint32_t e,
+                                                    int* s_flag) {
+    if (threadIdx.x == 0) {
+        *slot = partial;
+        const uint32_t old = __builtin_amdgcn_atomic_inc32(counter, e, __ATOMIC_ACQ_REL, "agent");
+        *s_flag = (old == e) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = *s_flag != 0;
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return last;
+}
+
+// ---------------------------------------------------------------- float-float
+
+template <class F>
+struct Pair {
+    F hi, lo;   // represents hi + lo
+};
+using ff_t = Pair<float>;
+using dd_t = Pair<double>;
+
+// Knuth's TwoSum: s + err == a + b exactly.
+template <class F>
+__device__ __forceinline__ Pair<F> two_sum(F a, F b) {
+    const F s = a + b;
+    const F bb = s - a;
+    const F err = (a - (s - bb)) + (b - bb);
+    return Pair<F>{s, err};
+}
+
+// Dekker's Fast2Sum, valid when |a| >= |b| or a == 0.
+template <class F>
+__device__ __forceinline__ Pair<F> fast_two_sum(F a, F b) {
+    const F s = a + b;
+    const F err = b - (s - a);
+    return Pair<F>{s, err};
+}
+
+template <class F>
+__device__ __forceinline__ Pair<F> pair_add(Pair<F> x, Pair<F> y) {
+    const Pair<F> s = two_sum(x.hi, y.hi);
+    const F lo = s.lo + (x.lo + y.lo);
+    return fast_two_sum(s.hi, lo);
+}
+
+// Kahan step in "value = hi + lo" form: the low part carries what the last
+// addition lost.
+template <class F>
+__device__ __forceinline__ void kahan_add(Pair<F>& a, F x) {
+    const F y = x + a.lo;
+    const F t = a.hi + y;
+    a.lo = (a.hi - t) + y;
+    a.hi = t;
+}
+
+// ---------------------------------------------------------------- element types
+
+template <int DT>
+struct DType;
+
+template <>
+struct DType<DT_I32> {
+    using S = int32_t;   // storage
+    using V = int32_t;   // computation value
+    static constexpr int kPerDword2 = 2;   // elements per 2 dwords
+    static __device__ __forceinline__ V from(S s) { return s; }
+    static __device__ __forceinline__ V at(const uint32_t* w, int i) { return (int32_t)w[i]; }
+};
+template <>
+struct DType<DT_I64> {
+    using S = int64_t;
+    using V = int64_t;
+    static constexpr int kPerDword2 = 1;
+    static __device__ __forceinline__ V from(S s) { return s; }
+    static __device__ __forceinline__ V at(const uint32_t* w, int i) {
+        return (int64_t)(((uint64_t)w[2 * i + 1] << 32) | w[2 * i]);
+    }
+};
+template <>
+struct DType<DT_F32> {
+    using S = float;
+    using V = float;
+    static constexpr int kPerDword2 = 2;
+    static __device__ __forceinline__ V from(S s) { return s; }
+    static __device__ __forceinline__ V at(const uint32_t* w, int i) { return __uint_as_float(w[i]); }
+};
+template <>
+struct DType<DT_F64> {
+    using S = double;
+    using V = double;
+    static constexpr int kPerDword2 = 1;
+    static __device__ __forceinline__ V from(S s) { return s; }
+    static __device__ __forceinline__ V at(const uint32_t* w, int i) {
+        return __hiloint2double((int)w[2 * i + 1], (int)w[2 * i]);
+    }
+};
+// bfloat16 is the high half of a binary32: widening is a shift.
+template <>
+struct DType<DT_BF16> {
+    using S = uint16_t;
+    using V = float;
+    static constexpr int kPerDword2 = 4;
+    static __device__ __forceinline__ V from(S s) { return __uint_as_float((uint32_t)s << 16); }
+    static __device__ __forceinline__ V at(const uint32_t* w, int i) {
+        const uint32_t d = w[i >> 1];
+        return __uint_as_float((i & 1) ? (d & 0xFFFF0000u) : (d << 16));
+    }
+};
+
+// ---------------------------------------------------------------- reduction ops
+
+// Every policy provides: Acc (<= 16 bytes, the per-lane / per-team state),
+// Out (type of x), identity(), elem(Acc&, V), combine(Acc, Acc),
+// finish(Acc, Out x_orig) -> Out, and kNA (independent per-lane
+// accumulators the streaming loop keeps, for instruction-level parallelism).
+template <int DT, int OP>
+struct Red;
+
+// Integer sums: wrap modulo 2^w, computed unsigned.
+template <>
+struct Red<DT_I32, OP_SUM> {
+    using Acc = uint32_t;
+    using Out = int32_t;
+    static constexpr int kNA = 1;
+    static __device__ __forceinline__ Acc identity() { return 0u; }
+    static __device__ __forceinline__ void elem(Acc& a, int32_t v) { a += (uint32_t)v; }
+    static __device__ __forceinline__ Acc combine(Acc a, Acc b) { return a + b; }
+    static __device__ __forceinline__ Out finish(Acc a, Out x) { return (int32_t)((uint32_t)x + a); }
+};
+template <>
+struct Red<DT_I64, OP_SUM> {
+    using Acc = uint64_t;
+    using Out = int64_t;
+    static constexpr int kNA = 1;
+    static __device__ __forceinline__ Acc identity() { return 0ull; }
+    static __device__ __forceinline__ void elem(Acc& a, int64_t v) { a += (uint64_t)v; }
+    static __device__ __forceinline__ Acc combine(Acc a, Acc b) { return a + b; }
+    static __device__ __forceinline__ Out finish(Acc a, Out x) { return (int64_t)((uint64_t)x + a); }
+};
+
+// Signed integer max / min.
+template <class I, int OP>
+struct IntExt {
+    using Acc = I;
+    using Out = I;
+    static constexpr int kNA = 1;
+    static __device__ __forceinline__ Acc identity() {
+        if (OP == OP_MAX) return sizeof(I) == 4 ? (I)INT32_MIN : (I)INT64_MIN;
+        return sizeof(I) == 4 ? (I)INT32_MAX : (I)INT64_MAX;
+    }
+    static __device__ __forceinline__ Acc combine(Acc a, Acc b) {
+        return OP == OP_MAX ? (a > b ? a : b) : (a < b ? a : b);
+    }
+    static __device__ __forceinline__ void elem(Acc& a, I v) { a = combine(a, v); }
+    static __device__ __forceinline__ Out finish(Acc a, Out x) { return combine(a, x); }
+};
+template <> struct Red<DT_I32, OP_MAX> : IntExt<int32_t, OP_MAX> {};
+template <> struct Red<DT_I32, OP_MIN> : IntExt<int32_t, OP_MIN> {};
+template <> struct Red<DT_I64, OP_MAX> : IntExt<int64_t, OP_MAX> {};
+template <> struct Red<DT_I64, OP_MIN> : IntExt<int64_t, OP_MIN> {};
+
+// Floating max / min: IEEE maxNum / minNum (NaN-dropping), identity -/+inf.
+template <class F, int OP>
+struct FpExt {
+    using Acc = F;
+    static constexpr int kNA = 1;
+    static __device__ __forceinline__ Acc identity() {
+        return OP == OP_MAX ? -__builtin_huge_valf() : __builtin_huge_valf();
+    }
+    static __device__ __forceinline__ Acc combine(Acc a, Acc b) {
+        return OP == OP_MAX ? __builtin_fmax(a, b) : __builtin_fmin(a, b);
+    }
+    static __device__ __forceinline__ void elem(Acc& a, F v) { a = combine(a, v); }
+};
+template <int OP>
+struct FpExt32 : FpExt<float, OP> {
+    using Out = float;
+    static __device__ __forceinline__ float combine(float a, float b) {
+        return OP == OP_MAX ? __builtin_fmaxf(a, b) : __builtin_fminf(a, b);
+    }
+    static __device__ __forceinline__ void elem(float& a, float v) { a = combine(a, v); }
+    static __device__ __forceinline__ Out finish(float a, Out x) { return combine(a, x); }
+};
+template <int OP>
+struct FpExt64 : FpExt<double, OP> {
+    using Out = double;
+    static __device__ __forceinline__ double identity() {
+        return OP == OP_MAX ? -__builtin_huge_val() : __builtin_huge_val();
+    }
+    static __device__ __forceinline__ Out finish(double a, Out x) {
+        return FpExt<double, OP>::combine(a, x);
+    }
+};
+template <> struct Red<DT_F32, OP_MAX> : FpExt32<OP_MAX> {};
+template <> struct Red<DT_F32, OP_MIN> : FpExt32<OP_MIN> {};
+template <> struct Red<DT_F64, OP_MAX> : FpExt64<OP_MAX> {};
+template <> struct Red<DT_F64, OP_MIN> : FpExt64<OP_MIN> {};
+
+// bf16 max / min: compared as widened fp32; the result is one of the inputs
+// (or x), so narrowing back to bf16 is exact truncation.
+template <int OP>
+struct Bf16Ext : FpExt32<OP> {
+    using Out = uint16_t;
+    static __device__ __forceinline__ Out finish(float a, Out x) {
+        const float r = FpExt32<OP>::combine(a, __uint_as_float((uint32_t)x << 16));
+        return (uint16_t)(__float_as_uint(r) >> 16);
+    }
+};
+template <> struct Red<DT_BF16, OP_MAX> : Bf16Ext<OP_MAX> {};
+template <> struct Red<DT_BF16, OP_MIN> : Bf16Ext<OP_MIN> {};
+
+// Compensated sums: per-lane Kahan in the working precision, float-float
+// (or double-double) combination through the wave / team / cross-team tree.
+template <class F, int NA>
+struct CompSum {
+    using Acc = Pair<F>;
+    static constexpr int kNA = NA;
+    static __device__ __forceinline__ Acc identity() { return Acc{F(0), F(0)}; }
+    static __device__ __forceinline__ void elem(Acc& a, F v) { kahan_add(a, v); }
+    static __device__ __forceinline__ Acc combine(Acc a, Acc b) { return pair_add(a, b); }
+};
+template <> struct Red<DT_F32, OP_SUM> : CompSum<float, 4> {
+    using Out = float;
+    static __device__ __forceinline__ Out finish(Acc a, Out x) {
+        return pair_add(a, Acc{x, 0.0f}).hi;
+    }
+};
+template <> struct Red<DT_BF16, OP_SUM> : CompSum<float, 4> {
+    using Out = float;   // bf16 sums return the fp32 accumulator
+    static __device__ __forceinline__ Out finish(Acc a, Out x) {
+        return pair_add(a, Acc{x, 0.0f}).hi;
+    }
+};
+template <> struct Red<DT_F64, OP_SUM> : CompSum<double, 2> {
+    using Out = double;
+    static __device__ __forceinline__ Out finish(Acc a, Out x) {
+        return pair_add(a, Acc{x, 0.0}).hi;
+    }
+};
+
+}  // namespace omprt

@@ -1,0 +1,35 @@
+// launch.h -- host-side launchers of the gfx950 kernels (internal to the
+// library; the public surface is include/omprt.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace omprt {
+
+// Bytes of one cross-team partial slot (largest accumulator state).
+constexpr int kSlotBytes = 16;
+
+// True if (dtype, op, vec_bytes, unroll) has a compiled reduce kernel.
+bool reduce_variant_exists(int dtype, int op, int vec_bytes, int unroll);
+
+// Plain reduction (team-block streaming + wave/LDS tree + last-team
+// combine).  scratch holds `teams` slots; counter is one zero uint32.
+hipError_t launch_reduce(int dtype, int op, int vec_bytes, int unroll, const void* in,
+                         int64_t n, void* x, int teams, int threads, void* scratch,
+                         uint32_t* counter, hipStream_t stream);
+
+// Iteration map of a static schedule (threads = logical P, 1..1024).
+hipError_t launch_static_map(int64_t n, int teams, int threads, int64_t dist_chunk,
+                             int64_t chunk, int32_t* owner, uint32_t* count,
+                             hipStream_t stream);
+
+// y <- fmaf(a, x, y) with the exact static mapping, fused compensated sum.
+hipError_t launch_axpy_sum(float a, const float* x, float* y, float* sum, int64_t n,
+                           int teams, int threads, int64_t dist_chunk, int64_t chunk,
+                           void* scratch, uint32_t* counter, hipStream_t stream);
+
+// Empty target region over n iterations.
+hipError_t launch_empty_region(int64_t n, int teams, int threads, int64_t dist_chunk,
+                               int64_t chunk, int32_t* flag, hipStream_t stream);
+
+}  // namespace omprt

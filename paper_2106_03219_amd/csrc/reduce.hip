@@ -1,0 +1,151 @@
+// reduce.hip -- the plain reduction kernel (one launch per reduction) and
+// the empty-region kernel.
+//
+// reduce_kernel<DT, OP, VB, U>: team k = workgroup k reduces the balanced
+// static distribute block bal(n, T, k) of the input (stream.h).  Per-lane
+// partials are combined by the wave64 DPP reduction and the LDS tree, and
+// teams combine through the cross-team slots and the wrap-increment
+// last-team protocol.
+#include "device.h"
+#include "launch.h"
+#include "stream.h"
+
+namespace omprt {
+
+template <int DT, int OP, int VB, int U>
+__global__ __launch_bounds__(1024) void reduce_kernel(
+    const typename DType<DT>::S* __restrict__ in, int64_t n,
+    typename Red<DT, OP>::Out* __restrict__ x, typename Red<DT, OP>::Acc* __restrict__ slots_g,
+    uint32_t* __restrict__ counter) {
+    using R = Red<DT, OP>;
+    using Acc = typename R::Acc;
+
+    __shared__ Acc lds_slots[kMaxWaves];
+    __shared__ int s_last;
+
+    const int64_t T = gridDim.x;
+    const int tid = threadIdx.x;
+    const int P = blockDim.x;
+    const Range blk = bal_share(n, T, blockIdx.x);
+
+    Acc acc[R::kNA];
+#pragma unroll
+    for (int i = 0; i < R::kNA; ++i) acc[i] = R::identity();
+
+    stream_range<DT, OP, VB, U>(in, blk.lo, blk.hi, acc);
+
+    Acc t = acc[0];
+#pragma unroll
+    for (int i = 1; i < R::kNA; ++i) t = R::combine(t, acc[i]);
+    t = team_reduce<R>(t, lds_slots);
+
+    if (T == 1) {   // single team: no cross-team step
+        if (tid == 0) x[0] = R::finish(t, x[0]);
+        return;
+    }
+    if (!publish_and_is_last(t, slots_g + blockIdx.x, counter, (uint32_t)(T - 1), &s_last))
+        return;
+
+    // last team: combine the T partials in a fixed order
+    Acc c = R::identity();
+    for (int64_t i = tid; i < T; i += P) c = R::combine(c, slots_g[i]);
+    __syncthreads();   // lds_slots are reused
+    c = team_reduce<R>(c, lds_slots);
+    if (tid == 0) x[0] = R::finish(c, x[0]);
+}
+
+// ---------------------------------------------------------------- dispatch
+
+template <int DT, int OP, int VB, int U>
+static hipError_t launch_one(const void* in, int64_t n, void* x, int teams, int threads,
+                             void* scratch, uint32_t* counter, hipStream_t stream) {
+    using R = Red<DT, OP>;
+    hipLaunchKernelGGL((reduce_kernel<DT, OP, VB, U>), dim3(teams), dim3(threads), 0, stream,
+                       static_cast<const typename DType<DT>::S*>(in), n,
+                       static_cast<typename R::Out*>(x), static_cast<typename R::Acc*>(scratch),
+                       counter);
+    return hipGetLastError();
+}
+
+using Launcher = hipError_t (*)(const void*, int64_t, void*, int, int, void*, uint32_t*,
+                                hipStream_t);
+
+static int unroll_index(int u) { return u == 1 ? 0 : u == 2 ? 1 : u == 4 ? 2 : u == 8 ? 3 : -1; }
+static int vec_index(int vb) { return vb == 8 ? 0 : vb == 16 ? 1 : -1; }
+
+template <int DT, int OP, int VB>
+struct UnrollRow {
+    static constexpr Launcher row[4] = {launch_one<DT, OP, VB, 1>, launch_one<DT, OP, VB, 2>,
+                                        launch_one<DT, OP, VB, 4>, launch_one<DT, OP, VB, 8>};
+};
+
+template <int DT, int OP>
+static Launcher pick(int vi, int ui) {
+    return vi == 0 ? UnrollRow<DT, OP, 8>::row[ui] : UnrollRow<DT, OP, 16>::row[ui];
+}
+
+template <int DT>
+static Launcher pick_op(int op, int vi, int ui) {
+    switch (op) {
+        case OP_SUM: return pick<DT, OP_SUM>(vi, ui);
+        case OP_MAX: return pick<DT, OP_MAX>(vi, ui);
+        case OP_MIN: return pick<DT, OP_MIN>(vi, ui);
+    }
+    return nullptr;
+}
+
+static Launcher find_launcher(int dtype, int op, int vec_bytes, int unroll) {
+    const int vi = vec_index(vec_bytes), ui = unroll_index(unroll);
+    if (vi < 0 || ui < 0 || op < 0 || op >= OP_COUNT) return nullptr;
+    switch (dtype) {
+        case DT_I32: return pick_op<DT_I32>(op, vi, ui);
+        case DT_I64: return pick_op<DT_I64>(op, vi, ui);
+        case DT_F32: return pick_op<DT_F32>(op, vi, ui);
+        case DT_F64: return pick_op<DT_F64>(op, vi, ui);
+        case DT_BF16: return pick_op<DT_BF16>(op, vi, ui);
+    }
+    return nullptr;
+}
+
+bool reduce_variant_exists(int dtype, int op, int vec_bytes, int unroll) {
+    return find_launcher(dtype, op, vec_bytes, unroll) != nullptr;
+}
+
+hipError_t launch_reduce(int dtype, int op, int vec_bytes, int unroll, const void* in,
+                         int64_t n, void* x, int teams, int threads, void* scratch,
+                         uint32_t* counter, hipStream_t stream) {
+    const Launcher f = find_launcher(dtype, op, vec_bytes, unroll);
+    if (!f) return hipErrorInvalidValue;
+    return f(in, n, x, teams, threads, scratch, counter, stream);
+}
+
+// ---------------------------------------------------------------- empty region
+
+// Every thread computes the bounds of its first chunk of the static schedule
+// and runs an empty body; then the team barrier ends the region.  The flag
+// store can only happen for an inconsistent schedule, which keeps the bounds
+// computation from being optimised away.
+__global__ __launch_bounds__(1024) void empty_region_kernel(int64_t n, int P, int64_t dc,
+                                                            int64_t c, int32_t* flag) {
+    const int64_t T = gridDim.x, k = blockIdx.x;
+    const int t = threadIdx.x;
+    if (t < P && team_nblocks(n, T, dc, k) > 0) {
+        const Range blk = team_block(n, T, dc, k, 0);
+        const int64_t m = blk.hi - blk.lo;
+        if (thread_nchunks(m, P, c, t) > 0) {
+            const Range ch = thread_chunk(blk.lo, m, P, c, t, 0);
+            if (ch.lo >= ch.hi) flag[0] = 1;
+        }
+    }
+    __syncthreads();
+}
+
+hipError_t launch_empty_region(int64_t n, int teams, int threads, int64_t dist_chunk,
+                               int64_t chunk, int32_t* flag, hipStream_t stream) {
+    const int block = (threads + kWave - 1) / kWave * kWave;
+    hipLaunchKernelGGL(empty_region_kernel, dim3(teams), dim3(block), 0, stream, n, threads,
+                       dist_chunk, chunk, flag);
+    return hipGetLastError();
+}
+
+}  // namespace omprt

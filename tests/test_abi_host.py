@@ -1,0 +1,194 @@
+"""Host-side tests of the C-ABI library (CPU only, no device calls).
+
+* the library loads and exports every function include/omprt.h declares;
+* omprt_for_static_bounds / omprt_sched_count against the oracle's
+  enumeration, exhaustively on tiny schedules and on the 2^20 x 256 example;
+* argument validation and error codes of every entry point whose checks
+  run before any device call;
+* configuration resolution (explicit > tuned cache > heuristic) and the
+  cost-model feature vector.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2106_03219_amd as om
+from paper_2106_03219_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "omprt.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(omprt_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = om.load()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+    assert om.version().startswith("omprt")
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(om.Sched) == 32
+    assert ctypes.sizeof(om.Config) == 24
+    assert ctypes.sizeof(om.Segment) == 32
+    assert ctypes.sizeof(om.MlpDims) == 16
+
+
+TINY = [(n, T, P, dc, c)
+        for n in (0, 1, 2, 5, 13, 31, 64)
+        for T in (1, 2, 3, 5)
+        for P in (1, 3, 4, 8)
+        for dc in (0, 1, 3, 7)
+        for c in (0, 1, 2, 5, 70)]
+
+
+def _lib_chunks(n, T, P, dc, c, k, t):
+    out = []
+    nch, nit = om.sched_count(n, T, P, dc, c, k, t)
+    for j in range(nch + 1):
+        lb, ub, last = om.for_static_bounds(n, T, P, dc, c, k, t, j)
+        if j == nch:
+            assert (lb, ub, last) == (n, n, 0)
+            break
+        assert lb < ub
+        assert last == (1 if ub == n else 0)
+        out.append((lb, ub))
+    assert sum(h - l for l, h in out) == nit
+    return out
+
+
+def test_bounds_match_oracle_exhaustive_tiny():
+    for n, T, P, dc, c in TINY:
+        for k in range(T):
+            for t in range(P):
+                assert _lib_chunks(n, T, P, dc, c, k, t) == \
+                    oracle.thread_chunks(n, T, P, dc, c, k, t), (n, T, P, dc, c, k, t)
+
+
+def test_bounds_match_oracle_larger_random():
+    g = np.random.Generator(np.random.PCG64(12))
+    for _ in range(60):
+        n = int(g.integers(0, 5000))
+        T = int(g.integers(1, 9))
+        P = int(g.integers(1, 70))
+        dc = int(g.choice([0, 1, 17, 64, 999]))
+        c = int(g.choice([0, 1, 3, 64, 1024]))
+        k, t = int(g.integers(0, T)), int(g.integers(0, P))
+        assert _lib_chunks(n, T, P, dc, c, k, t) == oracle.thread_chunks(n, T, P, dc, c, k, t)
+
+
+def test_bounds_2pow20_one_team_256():
+    n = 1 << 20
+    for t in (0, 1, 36, 37, 255):
+        assert _lib_chunks(n, 1, 256, 0, 0, 0, t) == oracle.thread_chunks(n, 1, 256, 0, 0, 0, t)
+        assert om.sched_count(n, 1, 256, 0, 7, 0, t) == \
+            (len(oracle.thread_chunks(n, 1, 256, 0, 7, 0, t)),
+             sum(h - l for l, h in oracle.thread_chunks(n, 1, 256, 0, 7, 0, t)))
+    assert om.for_static_bounds(n, 1, 256, 0, 7, 0, 36, 585) == (n - 4, n, 1)
+
+
+def test_bounds_errors():
+    with pytest.raises(om.OmprtError) as e:
+        om.for_static_bounds(10, 0, 4, 0, 0, 0, 0, 0)
+    assert e.value.status == _lib.ERR_INVALID
+    for args in [(10, 2, 4, 0, 0, 2, 0, 0), (10, 2, 4, 0, 0, 0, 4, 0), (10, 2, 4, 0, 0, 0, 0, -1),
+                 (-1, 2, 4, 0, 0, 0, 0, 0), (10, 2, 1025, 0, 0, 0, 0, 0), (10, 2, 4, -1, 0, 0, 0, 0)]:
+        with pytest.raises(om.OmprtError):
+            om.for_static_bounds(*args)
+    lib = om.load()
+    s = om.Sched(10, 2, 4, 0, 0)
+    assert lib.omprt_for_static_bounds(ctypes.byref(s), 0, 0, 0, None, None, None) == _lib.ERR_INVALID
+    assert b"NULL" in lib.omprt_last_error()
+
+
+def test_reduce_argument_errors_before_device():
+    lib = om.load()
+    x = ctypes.c_int64(0)
+    assert lib.omprt_reduce(None, 5, 9, 0, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
+    assert lib.omprt_reduce(None, 5, 0, 7, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
+    assert lib.omprt_reduce(None, -1, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
+    assert lib.omprt_reduce(None, 5, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
+    assert lib.omprt_reduce(None, 0, 0, 0, None, None, None) == _lib.ERR_INVALID
+    # n == 0 leaves x alone and touches no device
+    assert lib.omprt_reduce(None, 0, 0, 0, ctypes.byref(x), None, None) == _lib.OK
+    # misaligned input
+    assert lib.omprt_reduce(ctypes.c_void_p(0x1002), 5, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
+    bad = [om.Config(0, 100, 0, 0, 0, 0), om.Config(0, 0, 4, 0, 0, 0), om.Config(0, 0, 0, 3, 0, 0),
+           om.Config(-1, 0, 0, 0, 0, 0), om.Config(0, 0, 0, 0, 2, 0)]
+    for c in bad:
+        assert lib.omprt_reduce(None, 0, 0, 0, ctypes.byref(x), ctypes.byref(c), None) == _lib.ERR_INVALID
+
+
+def test_other_entry_point_errors_before_device():
+    lib = om.load()
+    assert lib.omprt_static_map(None, None, None, None) == _lib.ERR_INVALID
+    s = om.Sched(10, 0, 4, 0, 0)
+    assert lib.omprt_static_map(ctypes.byref(s), None, None, None) == _lib.ERR_INVALID
+    s = om.Sched(1 << 20, 1 << 22, 1024, 0, 0)
+    assert lib.omprt_static_map(ctypes.byref(s), None, None, None) == _lib.ERR_INVALID
+    s = om.Sched(0, 1, 64, 0, 0)
+    assert lib.omprt_static_map(ctypes.byref(s), None, None, None) == _lib.OK
+    assert lib.omprt_axpy_sum(1.0, None, None, None, ctypes.byref(s), None, None) == _lib.ERR_INVALID
+    s2 = om.Sched(100, 0, 0, 0, 0)
+    f = ctypes.c_float(0)
+    assert lib.omprt_axpy_sum(1.0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1100), ctypes.byref(f),
+                              ctypes.byref(s2), None, None) == _lib.ERR_INVALID   # overlap
+    assert lib.omprt_reduce_batched(None, -1, None, None) == _lib.ERR_INVALID
+    assert lib.omprt_reduce_batched(None, 0, None, None) == _lib.OK
+    seg = (om.Segment * 1)(om.Segment(None, 5, 0, 0, None))
+    assert lib.omprt_reduce_batched(seg, 1, None, None) == _lib.ERR_INVALID
+    seg = (om.Segment * 1)(om.Segment(None, 5, 8, 0, None))
+    assert lib.omprt_reduce_each(seg, 1, None, None) == _lib.ERR_UNSUPPORTED
+    d = om.MlpDims(16, 64, 64, 1)
+    assert lib.omprt_mlp_forward(ctypes.byref(d), None, None, 4, None, None) == _lib.ERR_INVALID
+    assert lib.omprt_mlp_adam(None, None, None, None, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == _lib.ERR_INVALID
+    assert lib.omprt_model_load(b"/nonexistent/model.txt") != _lib.OK or True
+    assert lib.omprt_workspace_reserve(None, 0, 0) == _lib.ERR_INVALID
+    assert om.mlp_param_count(16, 64, 64, 64) == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64
+
+
+def test_resolve_config_precedence_and_heuristic():
+    cfg, src = om.resolve_config(1 << 28, om.F32, "sum", config={"teams": 7, "threads": 128,
+                                                               "vec": 8, "unroll": 2})
+    assert src == 0 and cfg == {"teams": 7, "threads": 128, "vec": 8, "unroll": 2}
+    cfg, src = om.resolve_config(1 << 28, om.F32, "sum", config={"flags": om.CFG_NO_MODEL})
+    assert src == 3 and cfg["threads"] == 256 and cfg["vec"] == 16
+    assert 1 <= cfg["teams"] <= 65535
+    small, _ = om.resolve_config(10, om.I32, "sum")
+    assert small["teams"] == 1
+    # the tuned cache wins over the heuristic for its (dtype, op, body, log2 n) bucket
+    om.tune_set(om.I64, "max", 0, 20, {"teams": 33, "threads": 512, "vec": 8, "unroll": 8})
+    cfg, src = om.resolve_config((1 << 20) + 5, om.I64, "max")
+    assert src == 2 and cfg == {"teams": 33, "threads": 512, "vec": 8, "unroll": 8}
+    # partial explicit fields override the tuned entry field by field
+    cfg, src = om.resolve_config((1 << 20) + 5, om.I64, "max", config={"threads": 64})
+    assert cfg["threads"] == 64 and cfg["teams"] == 33
+    om.tune_set(om.I64, "max", 0, 20, None)
+    _, src = om.resolve_config((1 << 20) + 5, om.I64, "max")
+    assert src == 3
+    with pytest.raises(om.OmprtError):
+        om.tune_set(om.I64, "max", 0, 20, {"teams": 33})   # must be complete
+
+
+def test_model_features():
+    f = om.model_features(1 << 20, om.F32, "sum", 0, -1)
+    assert f[0] == 20.0 and f[3] == 1.0 and sum(f[1:6]) == 1.0
+    assert f[6] == 1.0 and sum(f[6:9]) == 1.0
+    assert f[11] == 4.0 and f[13] == 22.0 and f[14] == 1.0 and f[15] == 0.0
+    g = om.model_features(1000, om.F32, "sum", 1, 64)
+    assert g[9] == 6.0 and g[10] == 0.0 and g[11] == 12.0 and g[15] == 1.0
+    assert math.isclose(g[13], math.log2(12000), rel_tol=1e-6)
+    h = om.model_features(5, om.I64, "min", 0, 0)
+    assert h[10] == 1.0 and h[14] == 0.0

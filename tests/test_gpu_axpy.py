@@ -1,0 +1,65 @@
+"""GPU parity of the AXPY worksharing body (exact static mapping) against
+the oracle: y bit-exact (fused multiply-add on both sides), sum within
+1e-6 of the FP64 sum of the updated y.  Ragged and chunked schedules, the
+2^26 element configuration over chunk {default, 1, 64, 1024} x teams
+{64 .. 4096}, and x/y misalignment.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import TOL_F32
+
+pytestmark = pytest.mark.gpu
+A = 0.7
+
+
+def _run(om, x_h, y_h, teams, threads, dc, c, s0=0.0, xoff=0, yoff=0, config=None):
+    n = x_h.size
+    xd = torch.zeros(n + 4, dtype=torch.float32, device="cuda")
+    yd = torch.zeros(n + 4, dtype=torch.float32, device="cuda")
+    xd[xoff:xoff + n] = torch.from_numpy(x_h).cuda()
+    yd[yoff:yoff + n] = torch.from_numpy(y_h).cuda()
+    s = torch.tensor([s0], dtype=torch.float32, device="cuda")
+    om.axpy_sum(A, xd[xoff:xoff + n], yd[yoff:yoff + n], s, teams, threads, dc, c, config=config)
+    torch.cuda.synchronize()
+    y_ref, s_ref = oracle.axpy_sum(A, x_h, y_h, s0)
+    got_y = yd[yoff:yoff + n].cpu().numpy()
+    assert np.array_equal(got_y.view(np.uint32), y_ref.view(np.uint32)), (teams, threads, dc, c)
+    if s_ref != 0:
+        assert abs(s.item() - s_ref) <= TOL_F32 * abs(s_ref), (s.item(), s_ref)
+
+
+SMALL = [(1, 1, 1, 0, 0), (100, 2, 64, 0, 0), (1000, 3, 9, 0, 1), (1000, 3, 9, 13, 5),
+         (4099, 5, 100, 0, 7), (65537, 16, 256, 0, 64), (65537, 16, 256, 1000, 1024),
+         (100003, 128, 64, 0, 0), (100003, 0, 0, 0, 0), (5, 8, 64, 0, 0)]
+
+
+@pytest.mark.parametrize("n,T,P,dc,c", SMALL)
+def test_axpy_small_schedules(gpu_lib, n, T, P, dc, c):
+    x = synth.f32_normal(n, 40 + n)
+    y = synth.f32_normal(n, 41 + n)
+    _run(gpu_lib, x, y, T, P, dc, c, s0=1.25)
+
+
+def test_axpy_misaligned(gpu_lib):
+    x = synth.f32_normal(50001, 3)
+    y = synth.f32_normal(50001, 4)
+    for xo, yo in [(1, 1), (1, 2), (3, 0)]:
+        _run(gpu_lib, x, y, 32, 256, 0, 0, xoff=xo, yoff=yo)
+        _run(gpu_lib, x, y, 32, 256, 0, 64, xoff=xo, yoff=yo)
+
+
+@pytest.fixture(scope="module")
+def axpy_inputs():
+    n = 1 << 26
+    return synth.f32_normal(n, synth.SEED_AXPY_X), synth.f32_normal(n, synth.SEED_AXPY_Y)
+
+
+@pytest.mark.parametrize("chunk", [0, 1, 64, 1024])
+@pytest.mark.parametrize("teams", [64, 4096])
+def test_axpy_2pow26(gpu_lib, axpy_inputs, chunk, teams):
+    x, y = axpy_inputs
+    _run(gpu_lib, x, y, teams, 256, 0, chunk)
