@@ -139,21 +139,29 @@ __device__ __forceinline__ Pair<F> fast_two_sum(F a, F b) {
     return Pair<F>{s, err};
 }
 
+// Accurate float-float addition: both the high and the low parts go
+// through TwoSum, then two renormalisations (no cancellation assumption).
 template <class F>
 __device__ __forceinline__ Pair<F> pair_add(Pair<F> x, Pair<F> y) {
-    const Pair<F> s = two_sum(x.hi, y.hi);
-    const F lo = s.lo + (x.lo + y.lo);
-    return fast_two_sum(s.hi, lo);
+    Pair<F> s = two_sum(x.hi, y.hi);
+    const Pair<F> t = two_sum(x.lo, y.lo);
+    s.lo += t.hi;
+    s = fast_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return fast_two_sum(s.hi, s.lo);
 }
 
-// Kahan step in "value = hi + lo" form: the low part carries what the last
-// addition lost.
+// Compensated accumulation of one value: TwoSum captures the rounding error
+// of hi + x exactly whatever the magnitudes (a Kahan/Fast2Sum step would
+// need |hi| >= |x|, which sums crossing zero violate); the errors gather in
+// lo.  The pair represents hi + lo.
 template <class F>
-__device__ __forceinline__ void kahan_add(Pair<F>& a, F x) {
-    const F y = x + a.lo;
-    const F t = a.hi + y;
-    a.lo = (a.hi - t) + y;
-    a.hi = t;
+__device__ __forceinline__ void comp_add(Pair<F>& a, F x) {
+    const F s = a.hi + x;
+    const F bb = s - a.hi;
+    const F err = (a.hi - (s - bb)) + (x - bb);
+    a.hi = s;
+    a.lo += err;
 }
 
 // ---------------------------------------------------------------- element types
@@ -312,14 +320,15 @@ struct Bf16Ext : FpExt32<OP> {
 template <> struct Red<DT_BF16, OP_MAX> : Bf16Ext<OP_MAX> {};
 template <> struct Red<DT_BF16, OP_MIN> : Bf16Ext<OP_MIN> {};
 
-// Compensated sums: per-lane Kahan in the working precision, float-float
-// (or double-double) combination through the wave / team / cross-team tree.
+// Compensated sums: per-lane TwoSum accumulation in the working precision,
+// float-float (or double-double) combination through the wave / team /
+// cross-team tree.
 template <class F, int NA>
 struct CompSum {
     using Acc = Pair<F>;
     static constexpr int kNA = NA;
     static __device__ __forceinline__ Acc identity() { return Acc{F(0), F(0)}; }
-    static __device__ __forceinline__ void elem(Acc& a, F v) { kahan_add(a, v); }
+    static __device__ __forceinline__ void elem(Acc& a, F v) { comp_add(a, v); }
     static __device__ __forceinline__ Acc combine(Acc a, Acc b) { return pair_add(a, b); }
 };
 template <> struct Red<DT_F32, OP_SUM> : CompSum<float, 4> {

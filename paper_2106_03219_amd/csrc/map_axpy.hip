@@ -49,7 +49,7 @@ __device__ __forceinline__ void axpy_elem(float a, const float* __restrict__ x,
                                           float* __restrict__ y, int64_t i, ff_t& acc) {
     const float r = __builtin_fmaf(a, x[i], y[i]);
     y[i] = r;
-    kahan_add(acc, r);
+    comp_add(acc, r);
 }
 
 // One chunk [lo, hi) of the calling thread, 16-byte vectors where x and y
@@ -78,10 +78,10 @@ __device__ __forceinline__ void axpy_range(float a, const float* __restrict__ x,
         yy.z = __builtin_fmaf(a, xx.z, yy.z);
         yy.w = __builtin_fmaf(a, xx.w, yy.w);
         yv[j] = yy;
-        kahan_add(acc, yy.x);
-        kahan_add(acc, yy.y);
-        kahan_add(acc, yy.z);
-        kahan_add(acc, yy.w);
+        comp_add(acc, yy.x);
+        comp_add(acc, yy.y);
+        comp_add(acc, yy.z);
+        comp_add(acc, yy.w);
     }
     for (int64_t i = p + nv * 4; i < hi; ++i) axpy_elem(a, x, y, i, acc);
 }

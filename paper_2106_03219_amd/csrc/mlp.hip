@@ -2,7 +2,7 @@
 // forward (logits), mean softmax cross-entropy with its full backward pass,
 // and the Adam update, in fp32.  Shapes are tiny (F = 16, H = 64, K <= 64,
 // batches of a few hundred to tens of thousands of rows), so every kernel is
-// a plain one-thread-per-output VALU kernel; sums over batch rows use Kahan
+// a plain one-thread-per-output VALU kernel; sums over batch rows use TwoSum
 // compensation so the gradients track an FP64 reference closely.
 #include <math.h>
 #include <string.h>
@@ -51,7 +51,8 @@ __global__ void mlp_softmax_ce_kernel(const float* __restrict__ Z, const int32_t
     }
 }
 
-// GW[j][i] = sum_r D[r][j] A[r][i];  gb[j] = sum_r D[r][j]   (Kahan over r)
+// GW[j][i] = sum_r D[r][j] A[r][i];  gb[j] = sum_r D[r][j]   (compensated over r;
+// the product is rounded on its own so it is not fused into the TwoSum)
 __global__ void mlp_weight_grad_kernel(const float* __restrict__ D, const float* __restrict__ A,
                                        float* __restrict__ GW, float* __restrict__ gb, int B,
                                        int out, int in) {
@@ -60,11 +61,11 @@ __global__ void mlp_weight_grad_kernel(const float* __restrict__ D, const float*
     const int j = idx / (in + 1), i = idx % (in + 1);
     ff_t acc{0.0f, 0.0f};
     if (i == in) {
-        for (int r = 0; r < B; ++r) kahan_add(acc, D[(int64_t)r * out + j]);
+        for (int r = 0; r < B; ++r) comp_add(acc, D[(int64_t)r * out + j]);
         gb[j] = acc.hi + acc.lo;
     } else {
         for (int r = 0; r < B; ++r)
-            kahan_add(acc, D[(int64_t)r * out + j] * A[(int64_t)r * in + i]);
+            comp_add(acc, __fmul_rn(D[(int64_t)r * out + j], A[(int64_t)r * in + i]));
         GW[(int64_t)j * in + i] = acc.hi + acc.lo;
     }
 }
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(256) void mlp_mean_kernel(const float* __restrict__
                                                        float* __restrict__ out) {
     __shared__ ff_t slots[kMaxWaves];
     ff_t acc{0.0f, 0.0f};
-    for (int i = threadIdx.x; i < B; i += blockDim.x) kahan_add(acc, v[i]);
+    for (int i = threadIdx.x; i < B; i += blockDim.x) comp_add(acc, v[i]);
     acc = team_reduce<MeanPolicy>(acc, slots);
     if (threadIdx.x == 0) out[0] = (acc.hi + acc.lo) / (float)B;
 }

@@ -69,7 +69,10 @@ def test_adam_vs_oracle(gpu_lib):
     wd, md, vd, gd = (torch.from_numpy(a.copy()).cuda() for a in (w, m, v, gr))
     om.mlp_adam(wd, md, vd, gd, 7, lr=1e-2)
     torch.cuda.synchronize()
-    w2, m2, v2 = oracle.adam(w, m, v, gr, 7, lr=1e-2)
+    # the kernel receives fp32 hyperparameters: give the oracle the same values
+    f32 = lambda v: float(np.float32(v))
+    w2, m2, v2 = oracle.adam(w, m, v, gr, 7, lr=f32(1e-2), beta1=f32(0.9), beta2=f32(0.999),
+                             eps=f32(1e-8))
     assert _rel(wd.cpu().numpy(), w2) < 1e-6
     assert _rel(md.cpu().numpy(), m2) < 1e-6
     assert _rel(vd.cpu().numpy(), v2) < 1e-6

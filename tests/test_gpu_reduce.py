@@ -101,9 +101,8 @@ def test_all_dtypes_ops_ragged(gpu_lib, dtype):
 def test_nonzero_x_orig_and_empty(gpu_lib, dtype):
     om = gpu_lib
     host = synth.host(dtype, 5000, 77)
-    xs = {"sum": 5 if dtype in (synth.I32, synth.I64) else 2.5,
-          "max": 999999 if dtype in (synth.I32, synth.I64) else 1e3,
-          "min": -999999 if dtype in (synth.I32, synth.I64) else -1e3}
+    big = {synth.I32: 999999, synth.I64: 2**41}.get(dtype, 1e3)   # beyond the data's range
+    xs = {"sum": 5 if dtype in (synth.I32, synth.I64) else 2.5, "max": big, "min": -big}
     for op in OPS:
         got = _reduce_and_check(om, host, dtype, op, xs[op], None, 0, f"x_orig {op}")
         if op != "sum":
