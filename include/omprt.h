@@ -277,8 +277,19 @@ omprt_status omprt_tune_set(int32_t dtype, int32_t op, int32_t body,
 omprt_status omprt_workspace_reserve(void *hip_stream, int32_t max_teams,
                                      int32_t max_counters);
 
-/* Re-zero the stream's cross-team counters (after an aborted launch). */
+/* Re-zero the stream's cross-team counter and status (after an aborted
+ * launch).  Stream-ordered. */
 omprt_status omprt_workspace_reset(void *hip_stream);
+
+/*
+ * Synchronise the stream and report its workspace status: 0 = healthy,
+ * 1 = a last team gave up waiting for a partial that never arrived (its
+ * bounded poll expired; the result of that launch is not valid).  The
+ * cross-team step publishes partials as tagged agent-scope atomics and the
+ * last team polls for this launch's tag, so this only happens if a
+ * participant was lost (an aborted launch).
+ */
+omprt_status omprt_workspace_status(void *hip_stream, int32_t *h_status);
 
 /* Message of the last failed call on this host thread ("" if none). */
 const char *omprt_last_error(void);

@@ -18,7 +18,7 @@ __all__ = [
     "reduce_batched", "reduce_each", "make_segments", "axpy_sum", "empty_region",
     "mlp_param_count", "mlp_forward", "mlp_loss_grad", "mlp_adam", "model_load",
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
-    "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
+    "workspace_status", "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
     "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "CFG_NO_MODEL", "CFG_STATIC_TILES",
 ]
 
@@ -219,6 +219,13 @@ def workspace_reserve(max_teams, max_counters=0, stream=None):
 
 def workspace_reset(stream=None):
     check(load().omprt_workspace_reset(_stream(stream)), "workspace_reset")
+
+
+def workspace_status(stream=None) -> int:
+    """Synchronise the stream; 0 if every cross-team wait completed, 1 otherwise."""
+    v = ctypes.c_int32()
+    check(load().omprt_workspace_status(_stream(stream), ctypes.byref(v)), "workspace_status")
+    return v.value
 
 
 def finalize():

@@ -63,6 +63,7 @@ SIGNATURES = {
     "omprt_tune_set": (_i32, [_i32, _i32, _i32, _i32, _C]),
     "omprt_workspace_reserve": (_i32, [_p, _i32, _i32]),
     "omprt_workspace_reset": (_i32, [_p]),
+    "omprt_workspace_status": (_i32, [_p, ctypes.POINTER(_i32)]),
     "omprt_last_error": (ctypes.c_char_p, []),
     "omprt_version": (ctypes.c_char_p, []),
     "omprt_finalize": (_i32, []),

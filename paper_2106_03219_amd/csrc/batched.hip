@@ -9,9 +9,12 @@
 // reduction's team block; a multi-tile segment's tile partials go to fixed
 // slots and the segment's own wrap-increment counter (bound tiles - 1)
 // elects the tile that finishes last to combine them in tile order and
-// write x.  Results do not depend on which workgroup ran which tile.  The
-// launch is captured once into a HIP graph and replayed: counters and the
-// ticket reset themselves, so replays need no memset.
+// write x.  Slots are tagged with the launch epoch like the plain kernels'
+// (device.h); a launch-wide wrap-increment over finished segments elects the
+// workgroup that advances the epoch.  Results do not depend on which
+// workgroup ran which tile.  The launch is captured once into a HIP graph
+// and replayed: counters, ticket and epoch maintain themselves, so replays
+// need no memset.
 #include <string.h>
 
 #include <algorithm>
@@ -40,10 +43,24 @@ struct TileDesc {
     int32_t seg, pad;
 };
 
+// Device state of one plan: tagged slot per tile, election counter per
+// segment, tile ticket, finished-segment counter, epoch and status words.
+struct BatchState {
+    uint64_t* slots;
+    uint32_t* seg_counters;
+    uint32_t* ticket;
+    uint32_t* done;
+    uint32_t* epoch;
+    uint32_t* status;
+    int32_t ntiles;
+    int32_t nseg_active;   // segments with at least one tile
+};
+
+// Reduce one tile; returns true (team-uniform) if it completed its segment.
 template <int DT, int OP, int VB, int U>
-__device__ __forceinline__ void process_tile(const SegDesc& sd, const TileDesc& td, int tile,
-                                             char* __restrict__ slots, uint32_t* seg_counter,
-                                             void* lds_raw, int* s_last) {
+__device__ __forceinline__ bool process_tile(const SegDesc& sd, const TileDesc& td, int tile,
+                                             const BatchState& bs, uint32_t tag, void* lds_raw,
+                                             int* s_last) {
     using R = Red<DT, OP>;
     using Acc = typename R::Acc;
     Acc acc[R::kNA];
@@ -59,29 +76,26 @@ __device__ __forceinline__ void process_tile(const SegDesc& sd, const TileDesc& 
     typename R::Out* x = static_cast<typename R::Out*>(sd.x);
     if (sd.ntiles == 1) {
         if (threadIdx.x == 0) x[0] = R::finish(t, x[0]);
-        return;
+        return true;
     }
-    Acc* my_slot = reinterpret_cast<Acc*>(slots + (size_t)tile * kSlotBytes);
-    if (!publish_and_is_last(t, my_slot, seg_counter, (uint32_t)(sd.ntiles - 1), s_last)) return;
-    Acc c = R::identity();
-    for (int i = threadIdx.x; i < sd.ntiles; i += blockDim.x)
-        c = R::combine(c, *reinterpret_cast<const Acc*>(slots + (size_t)(sd.first_tile + i) *
-                                                                      kSlotBytes));
-    __syncthreads();
-    c = team_reduce<R>(c, lds);
+    if (!publish_and_elect(t, bs.slots + (size_t)tile * kSlotWords, bs.seg_counters + td.seg,
+                           (uint32_t)(sd.ntiles - 1), tag, s_last))
+        return false;
+    const Acc c = combine_slots<R>(bs.slots + (size_t)sd.first_tile * kSlotWords, sd.ntiles, tag,
+                                   bs.status, lds);
     if (threadIdx.x == 0) x[0] = R::finish(c, x[0]);
+    return true;
 }
 
 template <int VB, int U>
 __global__ __launch_bounds__(1024) void batched_kernel(const SegDesc* __restrict__ segs,
                                                        const TileDesc* __restrict__ tiles,
-                                                       int32_t ntiles, char* __restrict__ slots,
-                                                       uint32_t* __restrict__ seg_counters,
-                                                       uint32_t* __restrict__ ticket,
-                                                       int32_t use_ticket) {
+                                                       BatchState bs, int32_t use_ticket) {
     __shared__ Pair<double> lds[kMaxWaves];
     __shared__ int s_tile;
     __shared__ int s_last;
+    const uint32_t epoch = read_epoch(bs.epoch);
+    const uint32_t tag = launch_tag(epoch);
     int32_t next = blockIdx.x;
     for (;;) {
         __syncthreads();   // LDS from the previous tile is no longer read
@@ -89,21 +103,21 @@ __global__ __launch_bounds__(1024) void batched_kernel(const SegDesc* __restrict
         if (use_ticket) {
             if (threadIdx.x == 0)
                 s_tile = (int)__builtin_amdgcn_atomic_inc32(
-                    ticket, (uint32_t)(ntiles + gridDim.x - 1), __ATOMIC_RELAXED, "agent");
+                    bs.ticket, (uint32_t)(bs.ntiles + gridDim.x - 1), __ATOMIC_RELAXED, "agent");
             __syncthreads();
             tile = s_tile;
         } else {
             tile = next;
             next += gridDim.x;
         }
-        if (tile >= ntiles) break;
+        if (tile >= bs.ntiles) break;
         const TileDesc td = tiles[tile];
         const SegDesc sd = segs[td.seg];
-        uint32_t* ctr = seg_counters + td.seg;
+        bool seg_done = false;
         switch (sd.dtype * OP_COUNT + sd.op) {
-#define OMPRT_CASE(DT, OP)                                                       \
-    case DT * OP_COUNT + OP:                                                     \
-        process_tile<DT, OP, VB, U>(sd, td, tile, slots, ctr, lds, &s_last);     \
+#define OMPRT_CASE(DT, OP)                                                               \
+    case DT * OP_COUNT + OP:                                                             \
+        seg_done = process_tile<DT, OP, VB, U>(sd, td, tile, bs, tag, lds, &s_last);     \
         break;
             OMPRT_CASE(DT_I32, OP_SUM) OMPRT_CASE(DT_I32, OP_MAX) OMPRT_CASE(DT_I32, OP_MIN)
             OMPRT_CASE(DT_I64, OP_SUM) OMPRT_CASE(DT_I64, OP_MAX) OMPRT_CASE(DT_I64, OP_MIN)
@@ -113,11 +127,16 @@ __global__ __launch_bounds__(1024) void batched_kernel(const SegDesc* __restrict
 #undef OMPRT_CASE
             default: break;
         }
+        // the workgroup that completes the launch's last segment advances the epoch
+        if (seg_done && threadIdx.x == 0) {
+            const uint32_t e = (uint32_t)(bs.nseg_active - 1);
+            if (__builtin_amdgcn_atomic_inc32(bs.done, e, __ATOMIC_RELAXED, "agent") == e)
+                advance_epoch(bs.epoch, epoch);
+        }
     }
 }
 
-using BatchedKernel = void (*)(const SegDesc*, const TileDesc*, int32_t, char*, uint32_t*,
-                               uint32_t*, int32_t);
+using BatchedKernel = void (*)(const SegDesc*, const TileDesc*, BatchState, int32_t);
 
 static BatchedKernel batched_variant(int vec, int unroll) {
     if (vec == 16) {
@@ -149,6 +168,7 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t ntiles = 0;
+    uint32_t* status = nullptr;
     ~Plan() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -215,23 +235,27 @@ static omprt_status build_plan(Plan& p, hipStream_t user_stream) {
             td.push_back(TileDesc{t * te, std::min(g.n, (t + 1) * te), i, 0});
     }
     p.ntiles = (int32_t)td.size();
+    int32_t active = 0;
+    for (const SegDesc& d : sd) active += d.ntiles > 0 ? 1 : 0;
     const size_t seg_b = (sizeof(SegDesc) * (size_t)count + 255) / 256 * 256;
     const size_t tile_b = (sizeof(TileDesc) * td.size() + 255) / 256 * 256;
     const size_t slot_b = ((size_t)kSlotBytes * td.size() + 255) / 256 * 256;
-    const size_t ctr_b = ((size_t)(count + 1) * 4 + 255) / 256 * 256;
+    const size_t ctr_b = ((size_t)(count + 4) * 4 + 255) / 256 * 256;
     if (hipMalloc(&p.dmem, seg_b + tile_b + slot_b + ctr_b) != hipSuccess)
         return fail(OMPRT_ERR_NOMEM, "batched plan allocation failed");
     char* base = static_cast<char*>(p.dmem);
     SegDesc* d_seg = reinterpret_cast<SegDesc*>(base);
     TileDesc* d_tile = reinterpret_cast<TileDesc*>(base + seg_b);
-    char* d_slots = base + seg_b + tile_b;
     uint32_t* d_ctr = reinterpret_cast<uint32_t*>(base + seg_b + tile_b + slot_b);
-    uint32_t* d_ticket = d_ctr + count;
+    BatchState bs{reinterpret_cast<uint64_t*>(base + seg_b + tile_b), d_ctr, d_ctr + count,
+                  d_ctr + count + 1, d_ctr + count + 2, d_ctr + count + 3, p.ntiles, active};
     if (count) OMPRT_HIP(hipMemcpy(d_seg, sd.data(), sizeof(SegDesc) * sd.size(), hipMemcpyHostToDevice));
     if (!td.empty())
         OMPRT_HIP(hipMemcpy(d_tile, td.data(), sizeof(TileDesc) * td.size(), hipMemcpyHostToDevice));
-    OMPRT_HIP(hipMemsetAsync(d_ctr, 0, ctr_b, user_stream));   // once; counters self-reset
+    // once: zero slots (odd tags never match 0) and every counter
+    OMPRT_HIP(hipMemsetAsync(base + seg_b + tile_b, 0, slot_b + ctr_b, user_stream));
     OMPRT_HIP(hipStreamSynchronize(user_stream));
+    p.status = bs.status;
 
     BatchedKernel k = batched_variant(p.cfg.vec_bytes, p.cfg.unroll);
     if (!k) return fail(OMPRT_ERR_INVALID, "no batched kernel for vec %d unroll %d",
@@ -244,8 +268,8 @@ static omprt_status build_plan(Plan& p, hipStream_t user_stream) {
     const int32_t use_ticket = (p.cfg.flags & OMPRT_CFG_STATIC_TILES) ? 0 : 1;
     const int grid = std::max(1, std::min<int>(p.cfg.num_teams, std::max<int32_t>(p.ntiles, 1)));
     OMPRT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipLaunchKernelGGL(k, dim3(grid), dim3(p.cfg.threads_per_team), 0, cs, d_seg, d_tile,
-                       p.ntiles, d_slots, d_ctr, d_ticket, use_ticket);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(p.cfg.threads_per_team), 0, cs, d_seg, d_tile, bs,
+                       use_ticket);
     const hipError_t le = hipGetLastError();
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(cs, &g);
@@ -322,3 +346,12 @@ extern "C" omprt_status omprt_reduce_each(const omprt_segment* h_segs, int32_t c
     }
     return OMPRT_OK;
 }
+
+namespace omprt {
+// Status word of the stream's cached batched plan (nullptr if none).
+uint32_t* batched_status_word(int dev, hipStream_t stream) {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    auto it = g_plans.find({dev, stream});
+    return (it == g_plans.end() || !it->second) ? nullptr : it->second->status;
+}
+}  // namespace omprt

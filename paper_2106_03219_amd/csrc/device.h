@@ -90,27 +90,108 @@ __device__ __forceinline__ typename R::Acc team_reduce(typename R::Acc a,
     return a;
 }
 
-// Cross-team step.  Thread 0 stores the team's partial to its slot, then
-// performs the wrap-around increment  { v = *ctr; *ctr = v >= e ? 0 : v+1 }
-// with acquire-release ordering at agent scope (the release makes the slot
-// store visible before the increment; the device-wide fence behind the
-// OpenMP flush).  With e = participants - 1 exactly one team reads e: it is
-// the last, and it leaves the counter at 0 for the next launch or replay.
-// Returns the same bool in every thread of the team; the last team has also
-// executed an agent-scope acquire fence, so every partial is visible to it.
+// ---------------------------------------------------------------- cross-team
+
+// Cross-team state of one launch.  A participant (team, or tile of a batched
+// segment) publishes its partial into its slot; the wrap-around increment
+//   { v = *counter; *counter = v >= e ? 0 : v + 1 }   (e = participants - 1)
+// elects the one that reads e as the last; it combines every slot and leaves
+// the counter at 0 for the next launch or graph replay.
+//
+// Visibility without a per-team fence: every 64-bit slot word carries a
+// 32-bit payload and the launch's 32-bit tag and is written and read as an
+// agent-scope atomic (coherent across the XCDs' L2s).  The last participant
+// polls each word until it holds this launch's tag, so it never needs the
+// publishing stores to be ordered before the increments.  (An agent-scope
+// release fence per team -- the device-wide fence behind the OpenMP flush --
+// costs an L2 writeback on gfx950 and throttles the whole grid.)  The tag
+// comes from an epoch word in device memory that every participant reads at
+// start and the launch's finisher advances at the end, so graph replays get
+// fresh tags too.  Polls are bounded; a timeout sets *status.
+struct CrossTeam {
+    uint64_t* slots;     // kSlotWords words per participant
+    uint32_t* counter;   // election counter, 0 between launches
+    uint32_t* epoch;     // launch epoch
+    uint32_t* status;    // set to 1 if a poll timed out
+};
+constexpr int kSlotWords = 4;                 // 32-bit payload words per slot
+constexpr uint32_t kPollLimit = 1u << 22;     // polls per slot word before giving up
+
+__device__ __forceinline__ uint32_t read_epoch(const uint32_t* epoch) {
+    return __hip_atomic_load(const_cast<uint32_t*>(epoch), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void advance_epoch(uint32_t* epoch, uint32_t e) {
+    __hip_atomic_store(epoch, e + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Odd, so zero-filled slots never match.
+__device__ __forceinline__ uint32_t launch_tag(uint32_t epoch) { return (epoch << 1) | 1u; }
+
 template <class Acc>
-__device__ __forceinline__ bool publish_and_is_last(const Acc& partial, Acc* slot,
-                                                    uint32_t* counter, uint32_t e,
-                                                    int* s_flag) {
+__device__ __forceinline__ void publish_tagged(const Acc& v, uint64_t* slot, uint32_t tag) {
+    static_assert(sizeof(Acc) % 4 == 0 && sizeof(Acc) / 4 <= kSlotWords, "slot too small");
+    constexpr int W = sizeof(Acc) / 4;
+    uint32_t w[W];
+    __builtin_memcpy(w, &v, sizeof(Acc));
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+        __hip_atomic_store(slot + i, ((uint64_t)tag << 32) | w[i], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class Acc>
+__device__ __forceinline__ Acc collect_tagged(const uint64_t* slot, uint32_t tag,
+                                              uint32_t* status) {
+    constexpr int W = sizeof(Acc) / 4;
+    uint32_t w[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        uint64_t v;
+        uint32_t polls = 0;
+        for (;;) {
+            v = __hip_atomic_load(const_cast<uint64_t*>(slot + i), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(v >> 32) == tag) break;
+            if (++polls >= kPollLimit) {
+                __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        w[i] = (uint32_t)v;
+    }
+    Acc a;
+    __builtin_memcpy(&a, w, sizeof(Acc));
+    return a;
+}
+
+// Thread 0 publishes the team's partial and takes part in the election.
+// Returns the same bool in every thread of the team: true for the last.
+template <class Acc>
+__device__ __forceinline__ bool publish_and_elect(const Acc& partial, uint64_t* slot,
+                                                  uint32_t* counter, uint32_t e, uint32_t tag,
+                                                  int* s_flag) {
     if (threadIdx.x == 0) {
-        *slot = partial;
-        const uint32_t old = __builtin_amdgcn_atomic_inc32(counter, e, __ATOMIC_ACQ_REL, "agent");
+        publish_tagged(partial, slot, tag);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);   // keep the stores before the increment
+        const uint32_t old = __builtin_amdgcn_atomic_inc32(counter, e, __ATOMIC_RELAXED, "agent");
         *s_flag = (old == e) ? 1 : 0;
     }
     __syncthreads();
-    const bool last = *s_flag != 0;
-    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return last;
+    return *s_flag != 0;
+}
+
+// Last participant: combine slots [0, count) in index order (thread t takes
+// t, t + P, ...; then the team tree).  Result valid in thread 0.
+template <class R>
+__device__ __forceinline__ typename R::Acc combine_slots(const uint64_t* slots, int64_t count,
+                                                         uint32_t tag, uint32_t* status,
+                                                         typename R::Acc* lds) {
+    typename R::Acc c = R::identity();
+    for (int64_t i = threadIdx.x; i < count; i += blockDim.x)
+        c = R::combine(c, collect_tagged<typename R::Acc>(slots + i * kSlotWords, tag, status));
+    __syncthreads();   // lds may still be read by the previous tree
+    return team_reduce<R>(c, lds);
 }
 
 // ---------------------------------------------------------------- float-float

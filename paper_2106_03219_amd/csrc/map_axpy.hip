@@ -89,14 +89,13 @@ __device__ __forceinline__ void axpy_range(float a, const float* __restrict__ x,
 __global__ __launch_bounds__(1024) void axpy_sum_kernel(float a, const float* __restrict__ x,
                                                         float* __restrict__ y,
                                                         float* __restrict__ sum, int64_t n, int P,
-                                                        int64_t dc, int64_t c,
-                                                        ff_t* __restrict__ slots_g,
-                                                        uint32_t* __restrict__ counter) {
+                                                        int64_t dc, int64_t c, CrossTeam ct) {
     using R = Red<DT_F32, OP_SUM>;
     __shared__ ff_t lds_slots[kMaxWaves];
     __shared__ int s_last;
     const int64_t T = gridDim.x, k = blockIdx.x;
     const int t = threadIdx.x;
+    const uint32_t epoch = T > 1 ? read_epoch(ct.epoch) : 0u;
     ff_t acc = R::identity();
     if (t < P) {
         const int64_t nb = team_nblocks(n, T, dc, k);
@@ -115,20 +114,24 @@ __global__ __launch_bounds__(1024) void axpy_sum_kernel(float a, const float* __
         if (t == 0) sum[0] = R::finish(acc, sum[0]);
         return;
     }
-    if (!publish_and_is_last(acc, slots_g + k, counter, (uint32_t)(T - 1), &s_last)) return;
-    ff_t cmb = R::identity();
-    for (int64_t i = t; i < T; i += blockDim.x) cmb = R::combine(cmb, slots_g[i]);
-    __syncthreads();
-    cmb = team_reduce<R>(cmb, lds_slots);
-    if (t == 0) sum[0] = R::finish(cmb, sum[0]);
+    const uint32_t tag = launch_tag(epoch);
+    if (!publish_and_elect(acc, ct.slots + (size_t)k * kSlotWords, ct.counter, (uint32_t)(T - 1),
+                           tag, &s_last))
+        return;
+    const ff_t cmb = combine_slots<R>(ct.slots, T, tag, ct.status, lds_slots);
+    if (t == 0) {
+        sum[0] = R::finish(cmb, sum[0]);
+        advance_epoch(ct.epoch, epoch);
+    }
 }
 
 hipError_t launch_axpy_sum(float a, const float* x, float* y, float* sum, int64_t n, int teams,
-                           int threads, int64_t dist_chunk, int64_t chunk, void* scratch,
-                           uint32_t* counter, hipStream_t stream) {
+                           int threads, int64_t dist_chunk, int64_t chunk, const CrossTeamArgs& ct,
+                           hipStream_t stream) {
     const int block = (threads + kWave - 1) / kWave * kWave;
+    const CrossTeam dct{static_cast<uint64_t*>(ct.slots), ct.counter, ct.epoch, ct.status};
     hipLaunchKernelGGL(axpy_sum_kernel, dim3(teams), dim3(block), 0, stream, a, x, y, sum, n,
-                       threads, dist_chunk, chunk, static_cast<ff_t*>(scratch), counter);
+                       threads, dist_chunk, chunk, dct);
     return hipGetLastError();
 }
 

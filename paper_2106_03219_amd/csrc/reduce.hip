@@ -4,8 +4,8 @@
 // reduce_kernel<DT, OP, VB, U>: team k = workgroup k reduces the balanced
 // static distribute block bal(n, T, k) of the input (stream.h).  Per-lane
 // partials are combined by the wave64 DPP reduction and the LDS tree, and
-// teams combine through the cross-team slots and the wrap-increment
-// last-team protocol.
+// teams combine through tagged cross-team slots and the wrap-increment
+// last-team election (device.h).
 #include "device.h"
 #include "launch.h"
 #include "stream.h"
@@ -15,8 +15,7 @@ namespace omprt {
 template <int DT, int OP, int VB, int U>
 __global__ __launch_bounds__(1024) void reduce_kernel(
     const typename DType<DT>::S* __restrict__ in, int64_t n,
-    typename Red<DT, OP>::Out* __restrict__ x, typename Red<DT, OP>::Acc* __restrict__ slots_g,
-    uint32_t* __restrict__ counter) {
+    typename Red<DT, OP>::Out* __restrict__ x, CrossTeam ct) {
     using R = Red<DT, OP>;
     using Acc = typename R::Acc;
 
@@ -25,7 +24,7 @@ __global__ __launch_bounds__(1024) void reduce_kernel(
 
     const int64_t T = gridDim.x;
     const int tid = threadIdx.x;
-    const int P = blockDim.x;
+    const uint32_t epoch = T > 1 ? read_epoch(ct.epoch) : 0u;
     const Range blk = bal_share(n, T, blockIdx.x);
 
     Acc acc[R::kNA];
@@ -43,31 +42,34 @@ __global__ __launch_bounds__(1024) void reduce_kernel(
         if (tid == 0) x[0] = R::finish(t, x[0]);
         return;
     }
-    if (!publish_and_is_last(t, slots_g + blockIdx.x, counter, (uint32_t)(T - 1), &s_last))
+    const uint32_t tag = launch_tag(epoch);
+    if (!publish_and_elect(t, ct.slots + (size_t)blockIdx.x * kSlotWords, ct.counter,
+                           (uint32_t)(T - 1), tag, &s_last))
         return;
+    const Acc c = combine_slots<R>(ct.slots, T, tag, ct.status, lds_slots);
+    if (tid == 0) {
+        x[0] = R::finish(c, x[0]);
+        advance_epoch(ct.epoch, epoch);
+    }
+}
 
-    // last team: combine the T partials in a fixed order
-    Acc c = R::identity();
-    for (int64_t i = tid; i < T; i += P) c = R::combine(c, slots_g[i]);
-    __syncthreads();   // lds_slots are reused
-    c = team_reduce<R>(c, lds_slots);
-    if (tid == 0) x[0] = R::finish(c, x[0]);
+static CrossTeam to_device_ct(const CrossTeamArgs& a) {
+    return CrossTeam{static_cast<uint64_t*>(a.slots), a.counter, a.epoch, a.status};
 }
 
 // ---------------------------------------------------------------- dispatch
 
 template <int DT, int OP, int VB, int U>
 static hipError_t launch_one(const void* in, int64_t n, void* x, int teams, int threads,
-                             void* scratch, uint32_t* counter, hipStream_t stream) {
+                             const CrossTeamArgs& ct, hipStream_t stream) {
     using R = Red<DT, OP>;
     hipLaunchKernelGGL((reduce_kernel<DT, OP, VB, U>), dim3(teams), dim3(threads), 0, stream,
                        static_cast<const typename DType<DT>::S*>(in), n,
-                       static_cast<typename R::Out*>(x), static_cast<typename R::Acc*>(scratch),
-                       counter);
+                       static_cast<typename R::Out*>(x), to_device_ct(ct));
     return hipGetLastError();
 }
 
-using Launcher = hipError_t (*)(const void*, int64_t, void*, int, int, void*, uint32_t*,
+using Launcher = hipError_t (*)(const void*, int64_t, void*, int, int, const CrossTeamArgs&,
                                 hipStream_t);
 
 static int unroll_index(int u) { return u == 1 ? 0 : u == 2 ? 1 : u == 4 ? 2 : u == 8 ? 3 : -1; }
@@ -112,11 +114,11 @@ bool reduce_variant_exists(int dtype, int op, int vec_bytes, int unroll) {
 }
 
 hipError_t launch_reduce(int dtype, int op, int vec_bytes, int unroll, const void* in,
-                         int64_t n, void* x, int teams, int threads, void* scratch,
-                         uint32_t* counter, hipStream_t stream) {
+                         int64_t n, void* x, int teams, int threads, const CrossTeamArgs& ct,
+                         hipStream_t stream) {
     const Launcher f = find_launcher(dtype, op, vec_bytes, unroll);
     if (!f) return hipErrorInvalidValue;
-    return f(in, n, x, teams, threads, scratch, counter, stream);
+    return f(in, n, x, teams, threads, ct, stream);
 }
 
 // ---------------------------------------------------------------- empty region

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/omprt.h"
+#include "launch.h"
 
 namespace omprt {
 
@@ -25,15 +26,19 @@ constexpr int DT_COUNT_ABI = 5;   // OMPRT_I32 .. OMPRT_BF16
 int dtype_bytes(int dtype);         // storage bytes of an input element
 int out_bytes(int dtype, int op);   // bytes of x
 
-// Per (device, stream) workspace of the plain kernels: one cross-team
-// counter (zeroed once at allocation, self-resetting afterwards) and the
-// cross-team partial slots.
+// Per (device, stream) workspace of the plain kernels: a 256-byte header
+// (election counter, empty-region flag, launch epoch, poll-timeout status;
+// zeroed once at allocation, self-maintaining afterwards) followed by the
+// tagged cross-team slots.
 struct Workspace {
     void* base = nullptr;
     int32_t capacity = 0;   // slots
     uint32_t* counter() const { return static_cast<uint32_t*>(base); }
     int32_t* flag() const { return static_cast<int32_t*>(base) + 16; }
+    uint32_t* epoch() const { return static_cast<uint32_t*>(base) + 32; }
+    uint32_t* status() const { return static_cast<uint32_t*>(base) + 48; }
     void* slots() const { return static_cast<char*>(base) + 256; }
+    CrossTeamArgs cross() const { return CrossTeamArgs{slots(), counter(), epoch(), status()}; }
 };
 
 // Workspace of `stream` with room for `teams` slots, allocated or grown
@@ -49,6 +54,10 @@ enum ConfigSource { kSrcExplicit = 0, kSrcModel = 1, kSrcTuned = 2, kSrcHeuristi
 // tuned cache, else the heuristic.  body: 0 reduction, 1 AXPY.
 omprt_status resolve_config(int64_t n, int dtype, int op, int body, int64_t chunk,
                             const omprt_config* cfg, LaunchCfg* out, int* source);
+
+// Batched plans (batched.hip): free everything; status word of a stream's plan.
+void batched_finalize();
+uint32_t* batched_status_word(int dev, hipStream_t stream);
 
 // Learned picker (model.hip): true and *out filled when a model is loaded
 // and confident for these features.

@@ -164,7 +164,7 @@ def test_resolve_config_precedence_and_heuristic():
                                                                "vec": 8, "unroll": 2})
     assert src == 0 and cfg == {"teams": 7, "threads": 128, "vec": 8, "unroll": 2}
     cfg, src = om.resolve_config(1 << 28, om.F32, "sum", config={"flags": om.CFG_NO_MODEL})
-    assert src == 3 and cfg["threads"] == 256 and cfg["vec"] == 16
+    assert src == 3 and cfg["threads"] == 512 and cfg["vec"] == 16
     assert 1 <= cfg["teams"] <= 65535
     small, _ = om.resolve_config(10, om.I32, "sum")
     assert small["teams"] == 1

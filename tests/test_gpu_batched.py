@@ -85,6 +85,7 @@ def test_batched_many_replays_no_reset(gpu_lib):
         s = int(host.astype(object).sum())
         want = (reps * s + 2**63) % 2**64 - 2**63
         assert x.item() == want
+    assert om.workspace_status() == 0
 
 
 @pytest.mark.slow

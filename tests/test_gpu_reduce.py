@@ -206,6 +206,7 @@ def test_back_to_back_launches_self_reset(gpu_lib):
         om.reduce(ones, "sum", y, config={"teams": 1 + (r * 37) % 2048, "threads": 64})
     torch.cuda.synchronize()
     assert y.item() == 1000 * 5000
+    assert om.workspace_status() == 0      # no last team ever gave up waiting
 
 
 def test_separate_streams(gpu_lib):
