@@ -67,6 +67,215 @@ def cpu_baseline(f_host, i_host, passes: int):
                       f"over 2^28 each; {dt:.1f} s), FP64 Neumaier sums"}
 
 
+MODEL_FILE = os.path.join(ROOT, "paper_2106_03219_amd", "picker_model.txt")
+
+
+def _time_us(fn, torch, reps=5, inner=1):
+    """Min over reps of the duration of `inner` back-to-back calls (HIP events on the
+    current stream), per call, in microseconds."""
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(inner):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e3 / inner)
+    return best
+
+
+def bench_axpy(om, torch):
+    """AXPY + sum worksharing body over 2^26 fp32, chunk x teams sweep (256 threads)."""
+    import numpy as np
+    import oracle
+    import synth
+    _log("AXPY 2^26: parity and chunk x teams sweep")
+    n = 1 << 26
+    x = synth.device(synth.F32, n, synth.SEED_AXPY_X)
+    y0 = synth.device(synth.F32, n, synth.SEED_AXPY_Y)
+    y = y0.clone()
+    s = torch.zeros(1, dtype=torch.float32, device="cuda")
+    y_ref, s_ref = oracle.axpy_sum(0.7, x.cpu().numpy(), y0.cpu().numpy(), 0.0)
+    parity = {}
+    for c in (0, 1, 64, 1024):
+        y.copy_(y0)
+        s.zero_()
+        om.axpy_sum(0.7, x, y, s, 4096, 256, 0, c)
+        torch.cuda.synchronize()
+        parity[str(c)] = bool(np.array_equal(y.cpu().numpy().view(np.uint32), y_ref.view(np.uint32))
+                              and abs(s.item() - s_ref) <= 1e-6 * abs(s_ref))
+    table = {}
+    for c in (0, 1, 64, 1024):
+        for T in (64, 256, 1024, 4096):
+            us = _time_us(lambda: om.axpy_sum(0.7, x, y, s, T, 256, 0, c), torch)
+            table[f"c={c},T={T}"] = round(12 * n / us / 1e3, 1)
+    us = _time_us(lambda: om.axpy_sum(0.7, x, y, s), torch)
+    best = {str(c): max(v for k, v in table.items() if k.startswith(f"c={c},")) for c in (0, 1, 64, 1024)}
+    return {"n": n, "bytes_per_iter": 12, "gb_s": table, "best_gb_s_per_chunk": best,
+            "default_launch_gb_s": round(12 * n / us / 1e3, 1),
+            "parity_y_exact_sum_1e-6": parity}
+
+
+def bench_latency(om, torch):
+    """Launch latency of empty target regions and tiny reductions."""
+    import statistics
+    _log("launch latency sweep")
+    res = {}
+    stream = torch.cuda.current_stream()
+    for n in (0, 1, 16, 1024):
+        for T in (1, 64):
+            k = 2000
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                om.empty_region(n, T, 256)
+            t1 = time.perf_counter()
+            torch.cuda.synchronize()
+            b2b = _time_us(lambda: om.empty_region(n, T, 256), torch, reps=3, inner=k)
+            rt = []
+            for _ in range(200):
+                t2 = time.perf_counter()
+                om.empty_region(n, T, 256)
+                torch.cuda.synchronize()
+                rt.append((time.perf_counter() - t2) * 1e6)
+            res[f"empty n={n} T={T}"] = {"host_enqueue_us": round((t1 - t0) / k * 1e6, 2),
+                                         "back_to_back_us": round(b2b, 2),
+                                         "round_trip_us": round(statistics.median(rt), 2)}
+    a = torch.ones(1024, dtype=torch.int32, device="cuda")
+    x = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for n in (1, 1024):
+        b2b = _time_us(lambda: om.reduce(a[:n], "sum", x), torch, reps=3, inner=2000)
+        rt = []
+        for _ in range(200):
+            t2 = time.perf_counter()
+            om.reduce(a[:n], "sum", x)
+            torch.cuda.synchronize()
+            rt.append((time.perf_counter() - t2) * 1e6)
+        res[f"reduce int32 n={n}"] = {"back_to_back_us": round(b2b, 2),
+                                      "round_trip_us": round(statistics.median(rt), 2)}
+    # graph replay: 100 empty regions captured once on a side stream
+    s = torch.cuda.Stream()
+    om.workspace_reserve(64, stream=s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(100):
+            om.empty_region(16, 1, 256)
+    g.replay()
+    torch.cuda.synchronize()
+    rep = _time_us(lambda: g.replay(), torch, reps=5, inner=10)
+    res["graph replay of 100 empty regions: us per region"] = round(rep / 100, 3)
+    del stream
+    return res
+
+
+def _identity(om, dt, op):
+    import numpy as np
+    if op == "sum":
+        return 0
+    if dt in (om.I32, om.I64):
+        info = np.iinfo(np.int32 if dt == om.I32 else np.int64)
+        return int(info.min if op == "max" else info.max)
+    return float("-inf") if op == "max" else float("inf")
+
+
+def bench_batched(om, torch):
+    """4096 independent reductions (lengths log-uniform 1e2..1e7, int64/fp32/bf16, sum/max/min):
+    4096 plain launches (heuristic / learned configuration) vs one graph-replayed persistent
+    launch (default tiles / autotuned tiles).  A sample of segments is checked against the
+    oracle after each form."""
+    import numpy as np
+    import oracle
+    import synth
+    _log("batched: generating 4096 segments")
+    lens, dts, ops = synth.batched_spec(4096, synth.SEED_BATCH)
+    opn = {0: "sum", 1: "max", 2: "min"}
+    tdt = {om.I32: torch.int32, om.I64: torch.int64, om.F32: torch.float32, om.F64: torch.float64,
+           om.BF16: torch.bfloat16}
+    ins = [synth.device(int(dts[k]), int(lens[k]), 20_000 + k) for k in range(4096)]
+    meta = [(int(dts[k]), opn[int(ops[k])]) for k in range(4096)]
+    xs = []
+    for dt, op in meta:
+        xdt = torch.float32 if (dt == om.BF16 and op == "sum") else tdt[dt]
+        xs.append(torch.tensor([_identity(om, dt, op)], dtype=xdt, device="cuda"))
+    x0 = [x.clone() for x in xs]
+    segs = om.make_segments([(t, op, x) for t, x, (dt, op) in zip(ins, xs, meta)])
+    total_bytes = int(sum(t.numel() * t.element_size() for t in ins))
+    g = np.random.Generator(np.random.PCG64(6))
+    sample = sorted(set(g.integers(0, 4096, 24).tolist()) | {int(np.argmax(lens)), int(np.argmin(lens))})
+    refs = {}
+    for k in sample:
+        dt, op = meta[k]
+        t = ins[k]
+        if dt == om.BF16:
+            h = t.view(torch.int16).cpu().numpy().view(np.uint16)
+            refs[k] = oracle.reduce_fp(h, op, _identity(om, dt, op), bf16=True, want_abs=True)
+        elif dt in (om.I32, om.I64):
+            refs[k] = (oracle.reduce_int(t.cpu().numpy(), op, _identity(om, dt, op)), None)
+        else:
+            refs[k] = oracle.reduce_fp(t.cpu().numpy(), op, _identity(om, dt, op), want_abs=True)
+
+    def check(run):
+        for x, v in zip(xs, x0):
+            x.copy_(v)
+        run()
+        torch.cuda.synchronize()
+        worst = 0.0
+        for k in sample:
+            dt, op = meta[k]
+            ref, sabs = refs[k]
+            got = xs[k].float().item() if dt == om.BF16 and op != "sum" else xs[k].item()
+            if dt in (om.I32, om.I64) or op != "sum":
+                if got != ref:
+                    return False, None
+            else:
+                err = abs(got - ref) / abs(ref) if ref != 0 else abs(got) / sabs
+                worst = max(worst, err)
+                if err > 1e-6:
+                    return False, err
+        return True, worst
+
+    results, times = {}, {}
+
+    def measure(name, run):
+        ok, err = check(run)
+        us = _time_us(run, torch, reps=3)
+        times[name] = us
+        results[name] = {"ms": round(us / 1e3, 3), "reductions_per_s": round(4096 / (us * 1e-6), 1),
+                         "gb_s": round(total_bytes / us / 1e3, 1), "oracle_ok_1e-6": ok,
+                         "worst_rel_err_fp_sums": err}
+        _log(f"batched {name}: {us / 1e3:.3f} ms")
+
+    measure("plain_heuristic", lambda: om.reduce_each(segs, config={"flags": om.CFG_NO_MODEL}))
+    if os.path.exists(MODEL_FILE):
+        om.model_load(MODEL_FILE)
+        measure("plain_learned", lambda: om.reduce_each(segs))
+        om.model_load(None)
+    measure("batched_graph", lambda: om.reduce_batched(segs))
+    sweep = {}
+    for tk in (64, 256, 1024, 4096):
+        for th in (256, 512, 1024):
+            cfg = {"tile_kib": tk, "threads": th}
+            us = _time_us(lambda: om.reduce_batched(segs, config=cfg), torch, reps=3)
+            sweep[f"tile={tk}KiB,threads={th}"] = round(us / 1e3, 3)
+    best = min(sweep, key=sweep.get)
+    tk, th = [int(v.split("=")[1].rstrip("KiB")) for v in best.split(",")]
+    measure("batched_graph_tuned", lambda: om.reduce_batched(segs, config={"tile_kib": tk, "threads": th}))
+    results["batched_graph_tuned"]["config"] = {"tile_kib": tk, "threads": th}
+    out = {"segments": 4096, "bytes": total_bytes, "oracle_sample": len(sample), "forms": results,
+           "tile_sweep_ms": sweep,
+           "reductions_per_s": {k: v["reductions_per_s"] for k, v in results.items()}}
+    if "plain_learned" in times:
+        out["learned_vs_plain_speedup"] = round(times["plain_heuristic"] / times["plain_learned"], 3)
+    out["batched_vs_plain_speedup"] = round(times["plain_heuristic"] / times["batched_graph_tuned"], 2)
+    del ins
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +283,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-passes", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the AXPY, launch-latency and batched measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 3 device copies of 2^28 fp32 (1 GiB read + 1 GiB written), "
                          "the reference for scaling HBM byte counters")
@@ -163,6 +374,15 @@ def main():
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle")
         cpu = cpu_baseline(f_host, i_host, args.cpu_passes)
+    del f_host, i_host
+
+    extra = {}
+    if not args.no_extras:
+        del f, i
+        torch.cuda.empty_cache()
+        extra["axpy"] = bench_axpy(om, torch)
+        extra["latency"] = bench_latency(om, torch)
+        extra["batched"] = bench_batched(om, torch)
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
@@ -178,6 +398,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if "batched" in extra:
+        out["batched_reductions_per_s"] = extra["batched"]["reductions_per_s"]
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 
