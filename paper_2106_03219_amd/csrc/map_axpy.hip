@@ -70,7 +70,34 @@ __device__ __forceinline__ void axpy_range(float a, const float* __restrict__ x,
     const int64_t nv = (hi - p) / 4;
     const float4* __restrict__ xv = reinterpret_cast<const float4*>(x + p);
     float4* __restrict__ yv = reinterpret_cast<float4*>(y + p);
-    for (int64_t j = 0; j < nv; ++j) {
+    // four 16-byte vectors of x and of y in flight per lane: a lane's next
+    // loads hit the cache lines its previous ones brought in
+    constexpr int U = 4;
+    int64_t j = 0;
+    for (; j + U <= nv; j += U) {
+        float4 xx[U], yy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xx[u] = xv[j + u];
+            yy[u] = yv[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            yy[u].x = __builtin_fmaf(a, xx[u].x, yy[u].x);
+            yy[u].y = __builtin_fmaf(a, xx[u].y, yy[u].y);
+            yy[u].z = __builtin_fmaf(a, xx[u].z, yy[u].z);
+            yy[u].w = __builtin_fmaf(a, xx[u].w, yy[u].w);
+            yv[j + u] = yy[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            comp_add(acc, yy[u].x);
+            comp_add(acc, yy[u].y);
+            comp_add(acc, yy[u].z);
+            comp_add(acc, yy[u].w);
+        }
+    }
+    for (; j < nv; ++j) {
         const float4 xx = xv[j];
         float4 yy = yv[j];
         yy.x = __builtin_fmaf(a, xx.x, yy.x);
@@ -84,6 +111,32 @@ __device__ __forceinline__ void axpy_range(float a, const float* __restrict__ x,
         comp_add(acc, yy.w);
     }
     for (int64_t i = p + nv * 4; i < hi; ++i) axpy_elem(a, x, y, i, acc);
+}
+
+// Chunk size 1: thread t of the block [lo, hi) executes lo + t, lo + t + P,
+// ... (one-iteration chunks dealt round-robin).  A wave's lanes touch 64
+// consecutive elements, so every access is coalesced; four rows in flight.
+__device__ __forceinline__ void axpy_stride(float a, const float* __restrict__ x,
+                                            float* __restrict__ y, int64_t lo, int64_t hi,
+                                            int t, int P, ff_t& acc) {
+    constexpr int U = 4;
+    int64_t i = lo + t;
+    for (; i + (int64_t)(U - 1) * P < hi; i += (int64_t)U * P) {
+        float xx[U], yy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xx[u] = x[i + (int64_t)u * P];
+            yy[u] = y[i + (int64_t)u * P];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            yy[u] = __builtin_fmaf(a, xx[u], yy[u]);
+            y[i + (int64_t)u * P] = yy[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) comp_add(acc, yy[u]);
+    }
+    for (; i < hi; i += P) axpy_elem(a, x, y, i, acc);
 }
 
 __global__ __launch_bounds__(1024) void axpy_sum_kernel(float a, const float* __restrict__ x,
@@ -102,6 +155,10 @@ __global__ __launch_bounds__(1024) void axpy_sum_kernel(float a, const float* __
         for (int64_t i = 0; i < nb; ++i) {
             const Range blk = team_block(n, T, dc, k, i);
             const int64_t m = blk.hi - blk.lo;
+            if (c == 1) {   // the same iterations as the chunk loop below, strided
+                axpy_stride(a, x, y, blk.lo, blk.hi, t, P, acc);
+                continue;
+            }
             const int64_t nc = thread_nchunks(m, P, c, t);
             for (int64_t j = 0; j < nc; ++j) {
                 const Range ch = thread_chunk(blk.lo, m, P, c, t, j);

@@ -60,10 +60,25 @@ def predict(om, torch, params, X):
     return z.argmax(axis=1), p.max(axis=1)
 
 
-def evaluate(recs, pred):
+def picked_times(recs, pred, conf, tau):
+    """Time of the configuration the runtime would use: the predicted class when the
+    network's softmax confidence reaches tau, else the heuristic's."""
+    t = np.array([r["times_us"] for r in recs])
+    th = np.array([r["heuristic_us"] for r in recs])
+    tp = t[np.arange(len(recs)), pred]
+    return np.where(conf >= tau, tp, th)
+
+
+def choose_tau(recs, pred, conf, grid=(0.0, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7)):
+    """Confidence threshold minimising the geometric-mean time on the training set."""
+    best = min(grid, key=lambda tau: float(np.mean(np.log(picked_times(recs, pred, conf, tau)))))
+    return float(best)
+
+
+def evaluate(recs, pred, conf=None, tau=0.0):
     t = np.array([r["times_us"] for r in recs])
     best = t.min(axis=1)
-    tp = t[np.arange(len(recs)), pred]
+    tp = t[np.arange(len(recs)), pred] if conf is None else picked_times(recs, pred, conf, tau)
     th = np.array([r["heuristic_us"] for r in recs])
     regret = tp / best - 1.0
     h_regret = th / best - 1.0
@@ -133,7 +148,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--tau", type=float, default=0.0)
+    ap.add_argument("--tau", type=float, default=-1.0,
+                    help="confidence threshold; negative = choose on the training set")
     ap.add_argument("--seed", type=int, default=7)
     args = ap.parse_args(argv)
 
@@ -151,22 +167,29 @@ def main(argv=None):
     Xn = ((Xtr - mean) * scale).astype(np.float32)
     Xhn = ((Xho - mean) * scale).astype(np.float32)
     params = train(om, torch, Xn, ytr, args.epochs, args.batch, args.lr, args.seed)
-    pred_tr, _ = predict(om, torch, params, Xn)
+    pred_tr, conf_tr = predict(om, torch, params, Xn)
     pred_ho, conf_ho = predict(om, torch, params, Xhn)
+    tau = choose_tau(tr, pred_tr, conf_tr) if args.tau < 0 else args.tau
     p_host = params.cpu().numpy()
-    write_model(args.out, mean, scale, p_host, args.tau)
-    report = {"train": evaluate(tr, pred_tr), "heldout": evaluate(ho, pred_ho),
-              "train_label_accuracy": float(np.mean(pred_tr == ytr)),
+    write_model(args.out, mean, scale, p_host, tau)
+    report = {"train": evaluate(tr, pred_tr, conf_tr, tau),
+              "heldout": evaluate(ho, pred_ho, conf_ho, tau),
+              "heldout_model_only": evaluate(ho, pred_ho),
+              "heldout_fallback_fraction": float(np.mean(conf_ho < tau)),
+              "tau": tau, "train_label_accuracy": float(np.mean(pred_tr == ytr)),
               "classes": len(CLASSES), "epochs": args.epochs, "batch": args.batch, "lr": args.lr}
     # the runtime's C++ inference must reproduce the GPU network's choice
     om.model_load(args.out)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     from .tune import class_config
     agree = 0
-    for r, k in zip(ho, pred_ho):
+    for r, k, c in zip(ho, pred_ho, conf_ho):
         cfg, src = om.resolve_config(r["n"], r["dtype"], r["op"], r["body"], r["chunk"])
-        want = class_config(CLASSES[k], r["n"], 12 if r["body"] else {0: 4, 1: 8, 2: 4, 3: 8, 4: 2}[r["dtype"]], cus)
-        agree += int(src == 1 and cfg == want)
+        if c < tau:
+            agree += int(src != 1)
+            continue
+        bpi = 12 if r["body"] else {0: 4, 1: 8, 2: 4, 3: 8, 4: 2}[r["dtype"]]
+        agree += int(src == 1 and cfg == class_config(CLASSES[k], r["n"], bpi, cus))
     report["host_inference_agreement"] = agree / len(ho)
     om.model_load(None)
     print(json.dumps(report, indent=1))
