@@ -27,7 +27,6 @@ struct Model {
 
 static std::mutex g_model_mu;
 static Model* g_model = nullptr;
-static int g_cus = 0;
 
 static float log2f_pos(double v) { return v > 0 ? (float)log2(v) : 0.0f; }
 
@@ -55,7 +54,7 @@ void model_features(int64_t n, int dtype, int op, int body, int64_t chunk, float
 static int class_teams(const ClassCfg& c, int64_t n, int eb) {
     const int64_t per = (int64_t)c.threads * c.vec;
     const int64_t work = (n * eb + per - 1) / per;
-    int64_t t = (int64_t)c.teams_per_cu * g_cus;
+    int64_t t = (int64_t)c.teams_per_cu * device_cus();
     if (work < t) t = work;
     if (t < 1) t = 1;
     if (t > 65535) t = 65535;
@@ -159,9 +158,6 @@ extern "C" omprt_status omprt_model_load(const char* path) {
         g_model = nullptr;
         return OMPRT_OK;
     }
-    int dev = 0, cus = 0;
-    OMPRT_HIP(hipGetDevice(&dev));
-    OMPRT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     FILE* fp = fopen(path, "r");
     if (!fp) return fail(OMPRT_ERR_INVALID, "cannot open model file %s", path);
     Model* m = new Model();
@@ -174,7 +170,6 @@ extern "C" omprt_status omprt_model_load(const char* path) {
     std::lock_guard<std::mutex> lk(g_model_mu);
     delete g_model;
     g_model = m;
-    g_cus = cus;
     return OMPRT_OK;
 }
 

@@ -55,6 +55,9 @@ enum ConfigSource { kSrcExplicit = 0, kSrcModel = 1, kSrcTuned = 2, kSrcHeuristi
 omprt_status resolve_config(int64_t n, int dtype, int op, int body, int64_t chunk,
                             const omprt_config* cfg, LaunchCfg* out, int* source);
 
+// Compute units of the current device (256 if it cannot be queried).
+int device_cus();
+
 // Batched plans (batched.hip): free everything; status word of a stream's plan.
 void batched_finalize();
 uint32_t* batched_status_word(int dev, hipStream_t stream);

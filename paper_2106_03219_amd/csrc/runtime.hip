@@ -100,7 +100,7 @@ static int floor_log2(int64_t n) {
     return l;
 }
 
-static int device_cus() {
+int device_cus() {
     static int cached[64] = {0};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
