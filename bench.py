@@ -157,6 +157,19 @@ def bench_latency(om, torch):
             rt.append((time.perf_counter() - t2) * 1e6)
         res[f"reduce int32 n={n}"] = {"back_to_back_us": round(b2b, 2),
                                       "round_trip_us": round(statistics.median(rt), 2)}
+    # host cost without Python: 4096 one-element reductions issued from C in one call
+    ones = torch.ones(4096, dtype=torch.int64, device="cuda")
+    outs = torch.zeros(4096, dtype=torch.int64, device="cuda")
+    segs = om.make_segments([(ones[k:k + 1], "sum", outs[k:k + 1]) for k in range(4096)])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    om.reduce_each(segs, config={"flags": om.CFG_NO_MODEL})
+    t1 = time.perf_counter()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    res["4096 plain 1-element reductions issued from C"] = {
+        "host_enqueue_us_per_launch": round((t1 - t0) / 4096 * 1e6, 2),
+        "completion_us_per_launch": round((t2 - t0) / 4096 * 1e6, 2)}
     # graph replay: 100 empty regions captured once on a side stream
     s = torch.cuda.Stream()
     om.workspace_reserve(64, stream=s)

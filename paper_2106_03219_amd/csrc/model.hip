@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -61,10 +62,55 @@ static int class_teams(const ClassCfg& c, int64_t n, int eb) {
     return (int)t;
 }
 
-bool model_pick(const float* f16, int body, int64_t n, LaunchCfg* out) {
+// Decisions of the loaded model, keyed by the exact call properties, so a
+// repeated call skips the host forward pass (cleared when a model is loaded).
+struct PickKey {
+    int64_t n, chunk;
+    int dtype, op, body;
+    bool operator==(const PickKey& o) const {
+        return n == o.n && chunk == o.chunk && dtype == o.dtype && op == o.op && body == o.body;
+    }
+};
+struct PickKeyHash {
+    size_t operator()(const PickKey& k) const {
+        uint64_t h = (uint64_t)k.n * 0x9E3779B97F4A7C15ull;
+        h ^= (uint64_t)k.chunk + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
+        h ^= (uint64_t)(k.dtype * 16 + k.op * 4 + k.body) + (h << 6) + (h >> 2);
+        return (size_t)h;
+    }
+};
+struct PickVal {
+    bool have;
+    LaunchCfg cfg;
+};
+static std::unordered_map<PickKey, PickVal, PickKeyHash> g_pick_cache;
+constexpr size_t kPickCacheMax = 1 << 16;
+
+static bool model_forward_pick(const Model* m, const float* f16, int body, int64_t n,
+                               LaunchCfg* out);
+
+bool model_pick(int64_t n, int dtype, int op, int body, int64_t chunk, LaunchCfg* out) {
     std::lock_guard<std::mutex> lk(g_model_mu);
     const Model* m = g_model;
     if (!m) return false;
+    const PickKey key{n, chunk, dtype, op, body};
+    auto it = g_pick_cache.find(key);
+    if (it != g_pick_cache.end()) {
+        if (it->second.have) *out = it->second.cfg;
+        return it->second.have;
+    }
+    float f[16];
+    model_features(n, dtype, op, body, chunk, f);
+    PickVal v{false, LaunchCfg{}};
+    v.have = model_forward_pick(m, f, body, n, &v.cfg);
+    if (g_pick_cache.size() >= kPickCacheMax) g_pick_cache.clear();
+    g_pick_cache.emplace(key, v);
+    if (v.have) *out = v.cfg;
+    return v.have;
+}
+
+static bool model_forward_pick(const Model* m, const float* f16, int body, int64_t n,
+                               LaunchCfg* out) {
     float x[16], h1[4096], h2[4096], z[4096];
     for (int i = 0; i < m->F; ++i) x[i] = (f16[i] - m->mean[i]) * m->scale[i];
     const float* W1 = m->params.data();
@@ -155,6 +201,7 @@ extern "C" omprt_status omprt_model_load(const char* path) {
     if (!path) {
         std::lock_guard<std::mutex> lk(g_model_mu);
         delete g_model;
+    g_pick_cache.clear();
         g_model = nullptr;
         return OMPRT_OK;
     }
@@ -169,6 +216,7 @@ extern "C" omprt_status omprt_model_load(const char* path) {
     }
     std::lock_guard<std::mutex> lk(g_model_mu);
     delete g_model;
+    g_pick_cache.clear();
     g_model = m;
     return OMPRT_OK;
 }

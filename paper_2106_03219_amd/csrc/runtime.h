@@ -64,7 +64,7 @@ uint32_t* batched_status_word(int dev, hipStream_t stream);
 
 // Learned picker (model.hip): true and *out filled when a model is loaded
 // and confident for these features.
-bool model_pick(const float* features16, int body, int64_t n, LaunchCfg* out);
+bool model_pick(int64_t n, int dtype, int op, int body, int64_t chunk, LaunchCfg* out);
 void model_features(int64_t n, int dtype, int op, int body, int64_t chunk, float* f16);
 
 }  // namespace omprt

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -51,11 +52,28 @@ int out_bytes(int dtype, int op) {
 // ---------------------------------------------------------------- workspaces
 
 static std::mutex g_mu;
-static std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+static std::map<std::pair<int, hipStream_t>, Workspace> g_ws;   // node addresses are stable
+static std::atomic<uint64_t> g_ws_generation{1};                // bumped when workspaces are freed
+
+// Last workspace this host thread used: a repeat call on the same stream
+// skips the lock and the map (a stream is never shared between threads).
+struct WsMemo {
+    int dev = -1;
+    hipStream_t stream = nullptr;
+    Workspace* ws = nullptr;
+    uint64_t generation = 0;
+};
+static thread_local WsMemo t_ws;
 
 omprt_status workspace_get(hipStream_t stream, int32_t teams, Workspace** out) {
     int dev = 0;
     OMPRT_HIP(hipGetDevice(&dev));
+    if (t_ws.ws && t_ws.dev == dev && t_ws.stream == stream &&
+        t_ws.generation == g_ws_generation.load(std::memory_order_acquire) &&
+        t_ws.ws->capacity >= teams) {
+        *out = t_ws.ws;
+        return OMPRT_OK;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     Workspace& ws = g_ws[{dev, stream}];
     if (ws.capacity < teams) {
@@ -79,6 +97,7 @@ omprt_status workspace_get(hipStream_t stream, int32_t teams, Workspace** out) {
         // header and slots, once: tags are odd, so zeroed slots never match
         OMPRT_HIP(hipMemsetAsync(p, 0, 256 + (size_t)cap * kSlotBytes, stream));
     }
+    t_ws = WsMemo{dev, stream, &ws, g_ws_generation.load(std::memory_order_acquire)};
     *out = &ws;
     return OMPRT_OK;
 }
@@ -155,9 +174,7 @@ omprt_status resolve_config(int64_t n, int dtype, int op, int body, int64_t chun
     if (!full) {
         bool have = false;
         if (!(cfg && (cfg->flags & OMPRT_CFG_NO_MODEL))) {
-            float f[16];
-            model_features(n, dtype, op, body, chunk, f);
-            have = model_pick(f, body, n, &base);
+            have = model_pick(n, dtype, op, body, chunk, &base);
             if (have) src = kSrcModel;
         }
         if (!have) {
@@ -495,6 +512,7 @@ extern "C" omprt_status omprt_finalize(void) {
         (void)hipFree(kv.second.base);
     }
     g_ws.clear();
+    g_ws_generation.fetch_add(1, std::memory_order_acq_rel);
     OMPRT_HIP(hipSetDevice(dev));
     return OMPRT_OK;
 }
