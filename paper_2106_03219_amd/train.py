@@ -33,8 +33,14 @@ def load_db(path):
     return recs
 
 
+def abi_chunk(r):
+    """The chunk the runtime sees: an AXPY body without a user chunk runs
+    schedule(static) with no chunk size (0); reductions have none (-1)."""
+    return max(r["chunk"], 0) if r["body"] else -1
+
+
 def feature_matrix(om, recs):
-    return np.array([om.model_features(r["n"], r["dtype"], r["op"], r["body"], r["chunk"])
+    return np.array([om.model_features(r["n"], r["dtype"], r["op"], r["body"], abi_chunk(r))
                      for r in recs], dtype=np.float32)
 
 
@@ -184,7 +190,7 @@ def main(argv=None):
     from .tune import class_config
     agree = 0
     for r, k, c in zip(ho, pred_ho, conf_ho):
-        cfg, src = om.resolve_config(r["n"], r["dtype"], r["op"], r["body"], r["chunk"])
+        cfg, src = om.resolve_config(r["n"], r["dtype"], r["op"], r["body"], abi_chunk(r))
         if c < tau:
             agree += int(src != 1)
             continue
