@@ -230,3 +230,39 @@ def test_empty_region_sweep(gpu_lib):
             om.empty_region(n, T, 256)
             om.empty_region(n, T, 100, 3, 2)
     torch.cuda.synchronize()
+
+
+def test_plain_launches_under_caller_graph_capture(gpu_lib):
+    """Multi-team reductions captured into a caller's HIP graph and replayed many times,
+    with eager work between replays: every replay must reproduce the eager result
+    (the cross-team tags come from device memory, so replays never see stale slots)."""
+    om = gpu_lib
+    f = to_device(synth.f32_normal(3_000_001, 31), synth.F32)
+    i = to_device(synth.int64_uniform(2_000_003, 32), synth.I64)
+    s = torch.cuda.Stream()
+    om.workspace_reserve(4096, stream=s)
+    xs = torch.zeros(1, dtype=torch.float32, device="cuda")
+    xi = torch.zeros(1, dtype=torch.int64, device="cuda")
+    xm = torch.full((1,), -float("inf"), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    # eager reference on the same stream and configurations
+    with torch.cuda.stream(s):
+        om.reduce(f, "sum", xs, config={"teams": 777, "threads": 256})
+        om.reduce(i, "sum", xi, config={"teams": 1500, "threads": 512})
+        om.reduce(f, "max", xm, config={"teams": 300, "threads": 1024})
+    torch.cuda.synchronize()
+    want = (xs.item(), xi.item(), xm.item())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        om.reduce(f, "sum", xs, config={"teams": 777, "threads": 256})
+        om.reduce(i, "sum", xi, config={"teams": 1500, "threads": 512})
+        om.reduce(f, "max", xm, config={"teams": 300, "threads": 1024})
+    for rep in range(50):
+        xs.zero_(); xi.zero_(); xm.fill_(-float("inf"))
+        # unrelated eager launches on the default stream in between
+        om.reduce(f, "sum", torch.zeros(1, dtype=torch.float32, device="cuda"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert (xs.item(), xi.item(), xm.item()) == want, rep
+    assert om.workspace_status(stream=s) == 0
