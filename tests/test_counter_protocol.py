@@ -78,3 +78,61 @@ def test_nonzero_counter_is_detectable():
         if atomic_inc(mem, 0, 3) == 3:
             seen.append(k)
     assert seen == [1] and mem[0] == 2
+
+
+# ---------------------------------------------------------------- tagged slots
+
+def _launch_tagged(mem, partials, order, publish_delay, tag_of_launch):
+    """One launch of the tagged protocol.  mem holds 'counter', 'epoch' and slot words
+    (value, tag).  A team's slot store may become visible late (publish_delay[k]
+    increments after its own); the last team polls until every slot carries the
+    launch tag.  Returns the combined value the last team computes."""
+    T = len(partials)
+    epoch = mem["epoch"]
+    tag = tag_of_launch(epoch)
+    pending = []                        # (visible_after_step, slot, value)
+    step = 0
+    result = None
+    for k in order:
+        pending.append((step + publish_delay[k], k, partials[k]))
+        if atomic_inc(mem, "counter", T - 1) == T - 1:
+            # poll: the stores drain as time passes
+            while True:
+                for vis, slot, val in [p for p in pending if p[0] <= step]:
+                    mem["slots"][slot] = (val, tag)
+                pending = [p for p in pending if p[0] > step]
+                if all(mem["slots"][j][1] == tag for j in range(T)):
+                    break
+                step += 1
+            result = sum(mem["slots"][j][0] for j in range(T))
+            mem["epoch"] = epoch + 1
+        step += 1
+    return result
+
+
+def test_tagged_slots_tolerate_late_publication():
+    g = np.random.Generator(np.random.PCG64(5))
+    mem = {"counter": 0, "epoch": 0, "slots": [(0, 0)] * 8}
+    tag = lambda e: 2 * e + 1
+    for rep in range(300):
+        T = int(g.integers(2, 9))
+        partials = g.integers(-50, 50, T).tolist()
+        delays = g.integers(0, 6, T).tolist()
+        got = _launch_tagged(mem, partials, g.permutation(T), delays, tag)
+        assert got == sum(partials)
+        assert mem["counter"] == 0
+
+
+def test_epoch_from_memory_gives_fresh_tags_under_replay():
+    # a replayed graph freezes launch arguments: a tag passed as an argument would
+    # repeat, and a late store would let the last team read the previous replay's slot
+    mem = {"counter": 0, "epoch": 0, "slots": [(0, 0)] * 4}
+    frozen = lambda e: 7
+    first = _launch_tagged(mem, [1, 2, 3, 4], [0, 1, 2, 3], [0, 0, 0, 0], frozen)
+    assert first == 10
+    stale = _launch_tagged(mem, [10, 20, 30, 40], [0, 1, 2, 3], [0, 0, 5, 0], frozen)
+    assert stale != 100                 # read the old partial of team 2
+    mem = {"counter": 0, "epoch": 0, "slots": [(0, 0)] * 4}
+    fresh = lambda e: 2 * e + 1         # derived from the epoch word, advanced per launch
+    assert _launch_tagged(mem, [1, 2, 3, 4], [0, 1, 2, 3], [0, 0, 0, 0], fresh) == 10
+    assert _launch_tagged(mem, [10, 20, 30, 40], [0, 1, 2, 3], [0, 0, 5, 0], fresh) == 100
