@@ -266,3 +266,28 @@ def test_plain_launches_under_caller_graph_capture(gpu_lib):
         torch.cuda.synchronize()
         assert (xs.item(), xi.item(), xm.item()) == want, rep
     assert om.workspace_status(stream=s) == 0
+
+
+@pytest.mark.slow
+def test_max_sizes(gpu_lib):
+    """Past 2^31 elements (64-bit indexing end to end) and the largest team count."""
+    om = gpu_lib
+    n = (1 << 31) + 12345
+    b = synth.device(synth.BF16, n, 77)
+    x = torch.zeros(1, dtype=torch.float32, device="cuda")
+    om.reduce(b, "sum", x)
+    xm = torch.full((1,), -float("inf"), dtype=torch.bfloat16, device="cuda")
+    om.reduce(b, "max", xm)
+    torch.cuda.synchronize()
+    h = to_host(b)
+    ref, sabs = oracle.reduce_fp(h, "sum", 0.0, bf16=True, want_abs=True)
+    check_value(x.item(), ref, sabs, synth.BF16, "sum", "bf16 sum 2^31+12345")
+    assert float(xm.float().item()) == oracle.reduce_fp(h, "max", -np.inf, bf16=True)
+    del b, h
+    torch.cuda.empty_cache()
+    a = synth.int64_uniform(1_000_003, 78)
+    ref = oracle.reduce_int(a, "sum", 0)
+    y = torch.zeros(1, dtype=torch.int64, device="cuda")
+    om.reduce(to_device(a, synth.I64), "sum", y, config={"teams": 65535, "threads": 64})
+    torch.cuda.synchronize()
+    assert y.item() == ref
