@@ -115,7 +115,10 @@ __device__ __forceinline__ void axpy_range(float a, const float* __restrict__ x,
 
 // Chunk size 1: thread t of the block [lo, hi) executes lo + t, lo + t + P,
 // ... (one-iteration chunks dealt round-robin).  A wave's lanes touch 64
-// consecutive elements, so every access is coalesced; four rows in flight.
+// consecutive elements, so every access is coalesced and covers whole cache
+// lines: the streams bypass cache residency (nontemporal), four rows in
+// flight.  (Nontemporal access is a loss for the per-lane runs of larger
+// chunks, whose lines are consumed by several successive loads.)
 __device__ __forceinline__ void axpy_stride(float a, const float* __restrict__ x,
                                             float* __restrict__ y, int64_t lo, int64_t hi,
                                             int t, int P, ff_t& acc) {
@@ -125,13 +128,13 @@ __device__ __forceinline__ void axpy_stride(float a, const float* __restrict__ x
         float xx[U], yy[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            xx[u] = x[i + (int64_t)u * P];
-            yy[u] = y[i + (int64_t)u * P];
+            xx[u] = __builtin_nontemporal_load(x + i + (int64_t)u * P);
+            yy[u] = __builtin_nontemporal_load(y + i + (int64_t)u * P);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             yy[u] = __builtin_fmaf(a, xx[u], yy[u]);
-            y[i + (int64_t)u * P] = yy[u];
+            __builtin_nontemporal_store(yy[u], y + i + (int64_t)u * P);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) comp_add(acc, yy[u]);
