@@ -107,15 +107,48 @@ def tune_instance(om, bufs, inst, cus, torch):
     else:
         inp = bufs.t[dt][:n]
         xo = bufs.x_for(dt, op)
+        cfgs = {}
         for cls in CLASSES:
             cfg = class_config(cls, n, bpi, cus)
             key = tuple(cfg.values())
             if key not in cache:
                 cache[key] = time_call(lambda: om.reduce(inp, op, xo, config=cfg), reps, torch)
+                cfgs[key] = cfg
             times.append(cache[key])
         hcfg, _ = om.resolve_config(n, dt, op, 0, -1, {"flags": om.CFG_NO_MODEL})
         t_heur = time_call(lambda: om.reduce(inp, op, xo, config=hcfg), reps, torch)
+        check_consistent(om, inp, dt, op, list(cfgs.values()) + [hcfg], torch)
     return times, t_heur
+
+
+def check_consistent(om, inp, dt, op, cfgs, torch):
+    """Every timed configuration must produce the same reduction from the identity:
+    bit-identical for integers and max/min, within 2e-6 relative for compensated
+    floating sums (each is within 1e-6 of the exact sum).  Raises otherwise."""
+    one = [bufs_identity(torch, dt, op) for _ in cfgs]
+    for cfg, x in zip(cfgs, one):
+        om.reduce(inp, op, x, config=cfg)
+    torch.cuda.synchronize()
+    vals = [float(x.float().item()) if x.dtype == torch.bfloat16 else x.item() for x in one]
+    if op == 0 and dt in (2, 3, 4):
+        ref = max(abs(v) for v in vals)
+        if ref > 0 and (max(vals) - min(vals)) > 2e-6 * ref:
+            raise RuntimeError(f"configurations disagree on a floating sum: {vals}")
+    elif len(set(vals)) != 1:
+        raise RuntimeError(f"configurations disagree: {vals}")
+
+
+def bufs_identity(torch, dt, op):
+    tdt = {0: torch.int32, 1: torch.int64, 2: torch.float32, 3: torch.float64,
+           4: torch.bfloat16}[dt]
+    if dt == 4 and op == 0:
+        tdt = torch.float32
+    if op == 0:
+        return torch.zeros(1, dtype=tdt, device="cuda")
+    if dt in (0, 1):
+        info = torch.iinfo(tdt)
+        return torch.full((1,), info.min if op == 1 else info.max, dtype=tdt, device="cuda")
+    return torch.full((1,), -float("inf") if op == 1 else float("inf"), dtype=tdt, device="cuda")
 
 
 def main(argv=None):
