@@ -194,7 +194,8 @@ static omprt_status check_segments(const omprt_segment* s, int32_t count) {
         const omprt_segment& g = s[i];
         if (g.dtype < 0 || g.dtype >= DT_COUNT_ABI || g.op < 0 || g.op > 2)
             return fail(OMPRT_ERR_UNSUPPORTED, "segment %d: dtype %d / op %d", i, g.dtype, g.op);
-        if (g.n < 0) return fail(OMPRT_ERR_INVALID, "segment %d: n < 0", i);
+        if (g.n < 0 || g.n > ((int64_t)1 << 50))
+            return fail(OMPRT_ERR_INVALID, "segment %d: n outside 0..2^50", i);
         if (!g.d_x) return fail(OMPRT_ERR_INVALID, "segment %d: x is NULL", i);
         if (g.n > 0 && !g.d_in) return fail(OMPRT_ERR_INVALID, "segment %d: input is NULL", i);
         if (reinterpret_cast<uintptr_t>(g.d_in) % (uintptr_t)dtype_bytes(g.dtype) ||

@@ -151,6 +151,9 @@ static LaunchCfg heuristic(int64_t n, int dtype, int body) {
 
 static bool valid_threads(int t) { return t >= 64 && t <= 1024 && t % 64 == 0; }
 
+// Largest trip count accepted (keeps every byte offset far from int64 overflow).
+constexpr int64_t kMaxTrip = (int64_t)1 << 50;
+
 omprt_status resolve_config(int64_t n, int dtype, int op, int body, int64_t chunk,
                             const omprt_config* cfg, LaunchCfg* out, int* source) {
     if (cfg) {
@@ -206,7 +209,8 @@ omprt_status resolve_config(int64_t n, int dtype, int op, int body, int64_t chun
 
 static omprt_status check_sched(const omprt_sched* s, bool allow_auto) {
     if (!s) return fail(OMPRT_ERR_INVALID, "schedule pointer is NULL");
-    if (s->n < 0) return fail(OMPRT_ERR_INVALID, "n = %lld < 0", (long long)s->n);
+    if (s->n < 0 || s->n > kMaxTrip)
+        return fail(OMPRT_ERR_INVALID, "n = %lld outside 0..2^50", (long long)s->n);
     const int lo = allow_auto ? 0 : 1;
     if (s->num_teams < lo)
         return fail(OMPRT_ERR_INVALID, "num_teams = %d < %d", s->num_teams, lo);
@@ -340,7 +344,8 @@ extern "C" omprt_status omprt_reduce(const void* d_in, int64_t n, int32_t dtype,
                                      void* d_x, const omprt_config* cfg, void* hip_stream) {
     if (dtype < 0 || dtype >= DT_COUNT_ABI) return fail(OMPRT_ERR_UNSUPPORTED, "dtype %d", dtype);
     if (op < 0 || op > 2) return fail(OMPRT_ERR_UNSUPPORTED, "op %d", op);
-    if (n < 0) return fail(OMPRT_ERR_INVALID, "n = %lld < 0", (long long)n);
+    if (n < 0 || n > kMaxTrip)
+        return fail(OMPRT_ERR_INVALID, "n = %lld outside 0..2^50", (long long)n);
     if (!d_x) return fail(OMPRT_ERR_INVALID, "x is NULL");
     if (n > 0 && !d_in) return fail(OMPRT_ERR_INVALID, "input is NULL with n > 0");
     if (omprt_status st = check_ptr_align(d_in, dtype_bytes(dtype), "input")) return st;
@@ -390,6 +395,8 @@ extern "C" omprt_status omprt_axpy_sum(float a, const float* d_x, float* d_y, fl
     if (omprt_status st = resolve_config(s->n, OMPRT_F32, OMPRT_SUM, 1, s->chunk, cfg, &lc, nullptr))
         return st;
     const int teams = s->num_teams ? s->num_teams : lc.teams;
+    if (teams > 65535)
+        return fail(OMPRT_ERR_INVALID, "num_teams %d above 65535 (cross-team slot limit)", teams);
     const int threads = s->threads_per_team ? s->threads_per_team : lc.threads;
     if (s->n == 0) return OMPRT_OK;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
