@@ -369,6 +369,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 3 device copies of 2^28 fp32 (1 GiB read + 1 GiB written), "
                          "the reference for scaling HBM byte counters")
+    ap.add_argument("--only-axpy", type=int, nargs=2, metavar=("TEAMS", "CHUNK"), default=None,
+                    help="only run 3 AXPY+sum launches over 2^26 with 256 threads (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -383,6 +385,17 @@ def main():
     om.load()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+
+    if args.only_axpy:
+        teams, chunk = args.only_axpy
+        x = synth.device(synth.F32, 1 << 26, synth.SEED_AXPY_X)
+        y = synth.device(synth.F32, 1 << 26, synth.SEED_AXPY_Y)
+        s = torch.zeros(1, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            om.axpy_sum(0.7, x, y, s, teams, 256, 0, chunk)
+        torch.cuda.synchronize()
+        _log(f"3 AXPY+sum launches over 2^26, {teams} teams x 256 threads, chunk {chunk}")
+        return
 
     if args.calibrate_copy:
         src = torch.ones(N, dtype=torch.float32, device="cuda")
