@@ -15,6 +15,8 @@ statement of each):
 * :func:`reduce_int`, :func:`reduce_fp` -- ``reduction(op:x)`` results:
   integer wrap arithmetic, FP64 Neumaier sums, fmax/fmin folds.
 * :func:`axpy_sum` -- the AXPY worksharing body with fused fmaf.
+* :func:`atomic_serial` -- the five device atomics (sec. 3.1) applied in
+  index order.
 * :func:`mlp_loss_grad`, :func:`adam` -- the learned-configuration
   extension's network in FP64 (not from the paper).
 """
@@ -72,6 +74,8 @@ def _load():
     lib.oracle_mlp_loss_grad.restype = ctypes.c_double
     lib.oracle_adam.argtypes = [p, p, p, p, i64, i64] + [ctypes.c_double] * 4
     lib.oracle_adam.restype = None
+    lib.oracle_atomic_serial.argtypes = [ctypes.c_int, p, i64, p, p, p, p, i64]
+    lib.oracle_atomic_serial.restype = i64
     _lib = lib
     return lib
 
@@ -179,3 +183,19 @@ def adam(w, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     g = np.ascontiguousarray(g, dtype=np.float64)
     _load().oracle_adam(_ptr(w), _ptr(m), _ptr(v), _ptr(g), w.size, t, lr, beta1, beta2, eps)
     return w, m, v
+
+
+ATOMIC_OPS = {"add": 0, "inc": 1, "max": 2, "exchange": 3, "cas": 4}
+
+
+def atomic_serial(op, target, index, e, d=None):
+    """Apply the atomics in index order; returns (new targets, old values, skipped)."""
+    t = np.array(target, dtype=np.uint32, copy=True)
+    index = np.ascontiguousarray(index, dtype=np.uint32)
+    e = np.ascontiguousarray(e, dtype=np.uint32)
+    dd = np.ascontiguousarray(d if d is not None else np.zeros_like(e), dtype=np.uint32)
+    old = np.zeros(index.size, dtype=np.uint32)
+    code = ATOMIC_OPS[op] if isinstance(op, str) else int(op)
+    sk = _load().oracle_atomic_serial(code, _ptr(t), t.size, _ptr(index), _ptr(e), _ptr(dd),
+                                      _ptr(old), index.size)
+    return t, old, int(sk)

@@ -402,3 +402,42 @@ void oracle_adam(double *w, double *m, double *v, const double *g, int64_t n,
         w[i] -= lr * mh / (sqrt(vh) + eps);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Device atomics                                                           */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The runtime's five atomic operations on 32-bit unsigned words, applied
+ * one after another in index order (one valid linearisation of concurrent
+ * execution).  Paper sec. 3.1 defines them: add { v = x; x += e; },
+ * max { v = x; if (x < e) x = e; } (unsigned), exchange { v = x; x = e; },
+ * cas { v = x; if (x == e) x = d; }, and inc { v = x; x = x >= e ? 0 : x+1; };
+ * each returns v.  op: 0 add, 1 inc, 2 max, 3 exchange, 4 cas.  An index at
+ * or beyond n_targets is skipped with old = 0xFFFFFFFF.  Returns the number
+ * of skipped operations.
+ */
+int64_t oracle_atomic_serial(int op, uint32_t *target, int64_t n_targets,
+                             const uint32_t *index, const uint32_t *e,
+                             const uint32_t *d, uint32_t *old, int64_t n)
+{
+    int64_t skipped = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if ((int64_t)index[i] >= n_targets) {
+            old[i] = 0xFFFFFFFFu;
+            skipped++;
+            continue;
+        }
+        uint32_t *x = &target[index[i]];
+        uint32_t v = *x;
+        switch (op) {
+        case 0: *x = v + e[i]; break;
+        case 1: *x = (v >= e[i]) ? 0u : v + 1u; break;
+        case 2: if (v < e[i]) *x = e[i]; break;
+        case 3: *x = e[i]; break;
+        case 4: if (v == e[i]) *x = d[i]; break;
+        }
+        old[i] = v;
+    }
+    return skipped;
+}
