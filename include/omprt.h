@@ -205,6 +205,41 @@ omprt_status omprt_axpy_sum(float a, const float *d_x, float *d_y,
 omprt_status omprt_empty_region(const omprt_sched *s, void *hip_stream);
 
 /* ----------------------------------------------------------------------- */
+/* Device atomics                                                          */
+/* ----------------------------------------------------------------------- */
+
+/* The five atomic operations of the device runtime (paper sec. 3.1, "Atomic
+ * Operations": add, max, exchange and cas as in the listing of OpenMP 5.1
+ * atomics, and inc as defined in its text and target-specific listing).
+ * Each returns the old value v of *X and updates *X (32-bit unsigned):
+ *   ADD      { v = *X; *X = *X + E; }                  (wraps mod 2^32)
+ *   INC      { v = *X; *X = (*X >= E) ? 0 : *X + 1; }
+ *   MAX      { v = *X; if (*X < E) *X = E; }           (unsigned compare)
+ *   EXCHANGE { v = *X; *X = E; }
+ *   CAS      { v = *X; if (*X == E) *X = D; }
+ * Sequentially consistent at agent scope (one GPU). */
+typedef enum {
+    OMPRT_ATOMIC_ADD = 0, OMPRT_ATOMIC_INC = 1, OMPRT_ATOMIC_MAX = 2,
+    OMPRT_ATOMIC_EXCHANGE = 3, OMPRT_ATOMIC_CAS = 4
+} omprt_atomic_op;
+
+/*
+ * n concurrent atomic operations, one per GPU thread: operation i acts on
+ * d_target[d_index[i]] with operand d_e[i] (and d_d[i] for CAS; d_d may be
+ * NULL otherwise) and stores the value it read in d_old[i].  Operations on
+ * the same target are linearised by the hardware in an unspecified order.
+ * d_index values must be < n_targets; the device checks: an operation whose
+ * index is out of range is not applied, its d_old[i] receives 0xFFFFFFFF and
+ * the stream's workspace status (omprt_workspace_status) becomes 2.  INVALID
+ * for op out of range, n < 0, n_targets < 1 with n > 0, NULL pointers
+ * (d_d may be NULL unless op is CAS).
+ */
+omprt_status omprt_atomic_apply(int32_t op, uint32_t *d_target, int64_t n_targets,
+                                const uint32_t *d_index, const uint32_t *d_e,
+                                const uint32_t *d_d, uint32_t *d_old, int64_t n,
+                                void *hip_stream);
+
+/* ----------------------------------------------------------------------- */
 /* Learned launch configuration (extension; not in the paper)              */
 /* ----------------------------------------------------------------------- */
 
@@ -282,12 +317,14 @@ omprt_status omprt_workspace_reserve(void *hip_stream, int32_t max_teams,
 omprt_status omprt_workspace_reset(void *hip_stream);
 
 /*
- * Synchronise the stream and report its workspace status: 0 = healthy,
- * 1 = a last team gave up waiting for a partial that never arrived (its
- * bounded poll expired; the result of that launch is not valid).  The
- * cross-team step publishes partials as tagged agent-scope atomics and the
- * last team polls for this launch's tag, so this only happens if a
- * participant was lost (an aborted launch).
+ * Synchronise the stream and report its workspace status, a bit set:
+ * 0 = healthy; bit 1 = a last team gave up waiting for a partial that never
+ * arrived (its bounded poll expired; the result of that launch is not
+ * valid -- the cross-team step publishes partials as tagged agent-scope
+ * atomics and the last team polls for this launch's tag, so this only
+ * happens if a participant was lost, e.g. an aborted launch); bit 2 = an
+ * omprt_atomic_apply operation had an out-of-range index.  The bits stay set
+ * until omprt_workspace_reset.
  */
 omprt_status omprt_workspace_status(void *hip_stream, int32_t *h_status);
 

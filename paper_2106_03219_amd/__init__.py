@@ -10,12 +10,14 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (BF16, CFG_NO_MODEL, CFG_STATIC_TILES, F32, F64, I32, I64, MAX, MIN, SUM,
+from ._lib import (ATOMIC_ADD, ATOMIC_CAS, ATOMIC_EXCHANGE, ATOMIC_INC, ATOMIC_MAX, BF16,
+                   CFG_NO_MODEL, CFG_STATIC_TILES, F32, F64, I32, I64, MAX, MIN, SUM,
                    Config, MlpDims, OmprtError, Sched, Segment, check)
 
 __all__ = [
     "load", "version", "for_static_bounds", "sched_count", "static_map", "reduce",
-    "reduce_batched", "reduce_each", "make_segments", "axpy_sum", "empty_region",
+    "reduce_batched", "reduce_each", "make_segments", "axpy_sum", "empty_region", "atomic_apply",
+    "ATOMIC_ADD", "ATOMIC_INC", "ATOMIC_MAX", "ATOMIC_EXCHANGE", "ATOMIC_CAS",
     "mlp_param_count", "mlp_forward", "mlp_loss_grad", "mlp_adam", "model_load",
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
     "workspace_status", "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
@@ -156,6 +158,21 @@ def axpy_sum(a, x, y, s, teams=0, threads=0, dist_chunk=0, chunk=0, config=None,
     check(load().omprt_axpy_sum(ctypes.c_float(a), _ptr(x) if x.numel() else None,
                                 _ptr(y) if y.numel() else None, _ptr(s), ctypes.byref(sch),
                                 _cfg(config), _stream(stream)), "axpy_sum")
+
+
+# ---------------------------------------------------------------- device atomics
+
+_ATOMICS = {"add": ATOMIC_ADD, "inc": ATOMIC_INC, "max": ATOMIC_MAX, "exchange": ATOMIC_EXCHANGE,
+            "cas": ATOMIC_CAS}
+
+
+def atomic_apply(op, target, index, e, old, d=None, stream=None):
+    """old[i] <- atomic op on target[index[i]] with operand e[i] (and d[i] for cas);
+    all uint32 (torch.int32 storage), one GPU thread per operation."""
+    code = _ATOMICS[op] if isinstance(op, str) else int(op)
+    check(load().omprt_atomic_apply(code, _ptr(target), target.numel(), _ptr(index), _ptr(e),
+                                    _ptr(d), _ptr(old), index.numel(), _stream(stream)),
+          "atomic_apply")
 
 
 # ---------------------------------------------------------------- learned picker

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libomprt.so")
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_NOMEM, ERR_DEVICE = range(5)
 I32, I64, F32, F64, BF16 = range(5)
 SUM, MAX, MIN = range(3)
+ATOMIC_ADD, ATOMIC_INC, ATOMIC_MAX, ATOMIC_EXCHANGE, ATOMIC_CAS = range(5)
 CFG_NO_MODEL = 0x1
 CFG_STATIC_TILES = 0x2
 
@@ -53,6 +54,7 @@ SIGNATURES = {
     "omprt_reduce_each": (_i32, [ctypes.POINTER(Segment), _i32, _C, _p]),
     "omprt_axpy_sum": (_i32, [_f32, _p, _p, _p, _S, _C, _p]),
     "omprt_empty_region": (_i32, [_S, _p]),
+    "omprt_atomic_apply": (_i32, [_i32, _p, _i64, _p, _p, _p, _p, _i64, _p]),
     "omprt_mlp_param_count": (_i64, [_D]),
     "omprt_mlp_forward": (_i32, [_D, _p, _p, _i32, _p, _p]),
     "omprt_mlp_loss_grad": (_i32, [_D, _p, _p, _p, _i32, _p, _p, _p]),

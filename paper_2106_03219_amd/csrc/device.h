@@ -153,7 +153,7 @@ __device__ __forceinline__ Acc collect_tagged(const uint64_t* slot, uint32_t tag
                                   __HIP_MEMORY_SCOPE_AGENT);
             if ((uint32_t)(v >> 32) == tag) break;
             if (++polls >= kPollLimit) {
-                __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);

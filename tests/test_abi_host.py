@@ -192,3 +192,14 @@ def test_model_features():
     assert math.isclose(g[13], math.log2(12000), rel_tol=1e-6)
     h = om.model_features(5, om.I64, "min", 0, 0)
     assert h[10] == 1.0 and h[14] == 0.0
+
+
+def test_atomic_apply_argument_errors():
+    lib = om.load()
+    p = ctypes.c_void_p(0x1000)
+    assert lib.omprt_atomic_apply(5, p, 1, p, p, None, p, 1, None) == _lib.ERR_INVALID
+    assert lib.omprt_atomic_apply(0, p, 0, p, p, None, p, 1, None) == _lib.ERR_INVALID
+    assert lib.omprt_atomic_apply(4, p, 1, p, p, None, p, 1, None) == _lib.ERR_INVALID  # cas needs d
+    assert lib.omprt_atomic_apply(0, None, 1, p, p, None, p, 1, None) == _lib.ERR_INVALID
+    assert lib.omprt_atomic_apply(0, p, 1, p, p, None, p, -1, None) == _lib.ERR_INVALID
+    assert lib.omprt_atomic_apply(0, None, 0, None, None, None, None, 0, None) == _lib.OK
