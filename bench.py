@@ -294,6 +294,26 @@ def bench_batched(om, torch):
     return out
 
 
+def bench_atomics(om, torch):
+    """Throughput of the five device atomics: 2^24 operations, uncontended (one word
+    each), on 256 words, and all on one word."""
+    _log("device atomics throughput")
+    n = 1 << 24
+    e = torch.ones(n, dtype=torch.int32, device="cuda")
+    d = torch.zeros(n, dtype=torch.int32, device="cuda")
+    old = torch.empty(n, dtype=torch.int32, device="cuda")
+    out = {}
+    for name, words in (("uncontended", n), ("256_words", 256), ("one_word", 1)):
+        target = torch.zeros(words, dtype=torch.int32, device="cuda")
+        index = (torch.arange(n, device="cuda", dtype=torch.int64) % words).to(torch.int32)
+        row = {}
+        for op in ("add", "inc", "max", "exchange", "cas"):
+            us = _time_us(lambda: om.atomic_apply(op, target, index, e, old, d=d), torch, reps=3)
+            row[op] = round(n / us / 1e3, 2)
+        out[name] = row
+    return {"ops": n, "gops_per_s": out}
+
+
 def bench_learned(om, torch, count=300):
     """The learned picker on a sample of the held-out instance distribution (seed 8,
     n <= 1e8): total and geometric-mean time with the model's launches vs the built-in
@@ -471,6 +491,7 @@ def main():
         extra["axpy"] = bench_axpy(om, torch)
         extra["latency"] = bench_latency(om, torch)
         extra["batched"] = bench_batched(om, torch)
+        extra["atomics"] = bench_atomics(om, torch)
         learned = bench_learned(om, torch)
         if learned is not None:
             extra["learned_picker_heldout"] = learned
