@@ -199,3 +199,18 @@ def atomic_serial(op, target, index, e, d=None):
     sk = _load().oracle_atomic_serial(code, _ptr(t), t.size, _ptr(index), _ptr(e), _ptr(dd),
                                       _ptr(old), index.size)
     return t, old, int(sk)
+
+
+def reduce_array(a2d, op, x, bf16=False):
+    """reduction(op: x[0:m]) over the rows of a row-major (rows, m) block:
+    x[j] (op) fold_i a2d[i, j] for every column j, each column folded exactly as
+    reduce_int / reduce_fp fold a 1-D array.  Returns a list of m results."""
+    a2d = np.asarray(a2d)
+    out = []
+    for j in range(a2d.shape[1]):
+        col = np.ascontiguousarray(a2d[:, j])
+        if col.dtype in (np.int32, np.int64):
+            out.append(reduce_int(col, op, x[j]))
+        else:
+            out.append(reduce_fp(col, op, x[j], bf16=bf16))
+    return out
