@@ -152,8 +152,8 @@ omprt_status omprt_static_map(const omprt_sched *s, int32_t *d_owner,
  * bf16 sums, whose *d_x is float (the fp32 accumulator).  Integer sums wrap
  * modulo 2^w; max/min compare signed (integers) or follow IEEE maxNum /
  * minNum (floating, NaN-dropping).  fp32 and bf16 sums accumulate in
- * compensated fp32 (per-lane Kahan, float-float combination); fp64 sums in
- * fp64.  n == 0 leaves *d_x unchanged.  The result is deterministic for a
+ * compensated fp32 (TwoSum per element, float-float combination); fp64 sums
+ * in compensated fp64 likewise.  n == 0 leaves *d_x unchanged.  The result is deterministic for a
  * fixed (n, configuration).  Teams follow the static distribute schedule
  * (team k reduces the balanced block bal(n, T, k)); inside a team lanes read
  * interleaved vectors, which no reduction body can observe.  The cross-team
@@ -164,6 +164,48 @@ omprt_status omprt_static_map(const omprt_sched *s, int32_t *d_owner,
 omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
                           int32_t op, void *d_x, const omprt_config *cfg,
                           void *hip_stream);
+
+/*
+ * Array-section reduction, reduction(op: x[0:m]) over a loop of `rows`
+ * iterations whose iteration i contributes d_in[i*m + j] to list item x[j]
+ * (d_in row-major, rows x m):
+ *     d_x[j] <- d_x[j] (op) fold(op, d_in[i*m + j] for i in [0, rows))
+ * for every j in [0, m).  Each list item is a reduction variable of its own
+ * (OpenMP reduction clause on an array section: a private copy per thread,
+ * combined like a scalar), so element types, x's type (m entries, float for
+ * bf16 sums), arithmetic and determinism are those of omprt_reduce.
+ * rows == 0 or m == 0 leaves d_x unchanged.  d_in and d_x need element
+ * alignment; a 16-byte aligned d_in streams in 16-byte vectors when its rows
+ * (whole, or cut into column tiles) keep that alignment, otherwise one
+ * element per load.  The runtime cuts the block into column tiles and row
+ * periods (omprt_reduce_array_plan); teams on one tile combine through
+ * tagged slots and wrap-around-increment elections, in groups of 16.
+ * cfg (may be NULL): num_teams is the total team count aimed at (default
+ * 2 per compute unit); threads_per_team 64..1024 in steps of 64 (default
+ * 256); unroll 1, 2, 4 or 8 loads in flight per lane (default 4; at most
+ * 4 with 16-byte loads).  A team's private copies (threads x unroll x
+ * elements per load) must fit 64 KiB of LDS: the default unroll is lowered
+ * until they do; with an explicit unroll the call falls back to element
+ * loads, and is INVALID if even those do not fit.  vec_bytes 0 or
+ * 16 (vectors where possible) or the element size (one element per load).
+ * The learned model and tuned cache are not consulted.
+ * Errors: UNSUPPORTED for dtype/op out of range; INVALID for rows or m
+ * negative, rows*m above 2^50, NULL or misaligned pointers, x overlapping
+ * in, bad cfg fields.
+ */
+omprt_status omprt_reduce_array(const void *d_in, int64_t rows, int64_t m,
+                                int32_t dtype, int32_t op, void *d_x,
+                                const omprt_config *cfg, void *hip_stream);
+
+/*
+ * The launch omprt_reduce_array would make (host only, no device work):
+ * h_out8 = {tile width W, rows per period R, column tiles, row teams per
+ * tile, election groups per tile, bytes per load, threads, unroll}.
+ * aligned16 says whether d_in would be 16-byte aligned.  rows, m >= 1.
+ */
+omprt_status omprt_reduce_array_plan(int64_t rows, int64_t m, int32_t dtype,
+                                     int32_t op, int32_t aligned16,
+                                     const omprt_config *cfg, int64_t *h_out8);
 
 /*
  * count independent reductions in ONE persistent kernel launch.  h_segs is
@@ -324,7 +366,8 @@ omprt_status omprt_workspace_reset(void *hip_stream);
  * atomics and the last team polls for this launch's tag, so this only
  * happens if a participant was lost, e.g. an aborted launch); bit 2 = an
  * omprt_atomic_apply operation had an out-of-range index.  The bits stay set
- * until omprt_workspace_reset.
+ * until omprt_workspace_reset (which also re-zeroes the array-reduction
+ * counters).
  */
 omprt_status omprt_workspace_status(void *hip_stream, int32_t *h_status);
 

@@ -129,6 +129,27 @@ def reduce(inp, op, x, config=None, stream=None, n=None):
                               _op(op), _ptr(x), _cfg(config), _stream(stream)), "reduce")
 
 
+def reduce_array(inp, rows, m, op, x, config=None, stream=None):
+    """x[j] <- x[j] (op) fold(op, inp[i*m + j] for i < rows), j < m (inp row-major)."""
+    if not inp.is_contiguous() or not x.is_contiguous():
+        raise ValueError("input and x must be contiguous")
+    rows, m = int(rows), int(m)
+    if rows * m > inp.numel() or m > x.numel():
+        raise ValueError("input or x is smaller than rows x m")
+    nz = rows > 0 and m > 0
+    check(load().omprt_reduce_array(_ptr(inp) if nz else None, rows, m, dtype_code(inp), _op(op),
+                                    _ptr(x) if nz else None, _cfg(config), _stream(stream)),
+          "reduce_array")
+
+
+def reduce_array_plan(rows, m, dtype, op, aligned16=True, config=None):
+    """(W, R, col_tiles, row_teams, groups, bytes_per_load, threads, unroll) of a launch."""
+    out = (ctypes.c_int64 * 8)()
+    check(load().omprt_reduce_array_plan(int(rows), int(m), int(dtype), _op(op), int(aligned16),
+                                         _cfg(config), out), "reduce_array_plan")
+    return tuple(int(v) for v in out)
+
+
 def make_segments(items):
     """ctypes Segment array from [(input tensor, op, x tensor[, n]), ...]."""
     arr = (Segment * len(items))()

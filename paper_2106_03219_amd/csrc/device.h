@@ -139,27 +139,33 @@ __device__ __forceinline__ void publish_tagged(const Acc& v, uint64_t* slot, uin
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ uint64_t load_slot_word(const uint64_t* w) {
+    return __hip_atomic_load(const_cast<uint64_t*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Poll one slot word until it carries `tag` (bounded; a timeout sets bit 1
+// of *status and returns whatever the word holds).
+__device__ __forceinline__ uint64_t poll_slot_word(const uint64_t* w, uint32_t tag,
+                                                   uint32_t* status) {
+    uint32_t polls = 0;
+    for (;;) {
+        const uint64_t v = load_slot_word(w);
+        if ((uint32_t)(v >> 32) == tag) return v;
+        if (++polls >= kPollLimit) {
+            __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return v;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 template <class Acc>
 __device__ __forceinline__ Acc collect_tagged(const uint64_t* slot, uint32_t tag,
                                               uint32_t* status) {
     constexpr int W = sizeof(Acc) / 4;
     uint32_t w[W];
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-        uint64_t v;
-        uint32_t polls = 0;
-        for (;;) {
-            v = __hip_atomic_load(const_cast<uint64_t*>(slot + i), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-            if ((uint32_t)(v >> 32) == tag) break;
-            if (++polls >= kPollLimit) {
-                __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        w[i] = (uint32_t)v;
-    }
+    for (int i = 0; i < W; ++i) w[i] = (uint32_t)poll_slot_word(slot + i, tag, status);
     Acc a;
     __builtin_memcpy(&a, w, sizeof(Acc));
     return a;

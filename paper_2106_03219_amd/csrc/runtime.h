@@ -62,6 +62,12 @@ int device_cus();
 void batched_finalize();
 uint32_t* batched_status_word(int dev, hipStream_t stream);
 
+// Array-section reductions (array.hip): free everything; status word of a
+// stream's workspace; re-zero its counters and status.
+void array_finalize();
+uint32_t* array_status_word(int dev, hipStream_t stream);
+omprt_status array_reset(int dev, hipStream_t stream);
+
 // Learned picker (model.hip): true and *out filled when a model is loaded
 // and confident for these features.
 bool model_pick(int64_t n, int dtype, int op, int body, int64_t chunk, LaunchCfg* out);

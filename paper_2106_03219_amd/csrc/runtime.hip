@@ -473,6 +473,7 @@ extern "C" omprt_status omprt_workspace_reset(void* hip_stream) {
     int dev = 0;
     OMPRT_HIP(hipGetDevice(&dev));
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (omprt_status st = array_reset(dev, stream)) return st;
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_ws.find({dev, stream});
     if (it == g_ws.end() || !it->second.base) return OMPRT_OK;
@@ -494,12 +495,14 @@ extern "C" omprt_status omprt_workspace_status(void* hip_stream, int32_t* h_stat
         auto it = g_ws.find({dev, stream});
         if (it != g_ws.end() && it->second.base) st = it->second.status();
     }
-    uint32_t v = 0, vb = 0;
+    uint32_t v = 0, vb = 0, va = 0;
     OMPRT_HIP(hipStreamSynchronize(stream));
     if (st) OMPRT_HIP(hipMemcpy(&v, st, 4, hipMemcpyDeviceToHost));
     if (uint32_t* bst = batched_status_word(dev, stream))
         OMPRT_HIP(hipMemcpy(&vb, bst, 4, hipMemcpyDeviceToHost));
-    *h_status = (int32_t)(v | vb);
+    if (uint32_t* ast = array_status_word(dev, stream))
+        OMPRT_HIP(hipMemcpy(&va, ast, 4, hipMemcpyDeviceToHost));
+    *h_status = (int32_t)(v | vb | va);
     return OMPRT_OK;
 }
 
@@ -512,6 +515,7 @@ extern "C" omprt_status omprt_finalize(void) {
     OMPRT_HIP(hipGetDevice(&dev));
     OMPRT_HIP(hipDeviceSynchronize());
     batched_finalize();
+    array_finalize();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_ws) {
         if (!kv.second.base) continue;

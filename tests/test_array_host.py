@@ -1,0 +1,143 @@
+"""Host checks of the array-section reduction (no GPU): argument errors, and
+the launch geometry's index arithmetic replayed on the CPU.
+
+The replay follows the kernel's mapping from the plan the library reports:
+team (c, r) -> tile c, balanced periods of row team r; lane slot (u, t)
+covers flat offsets o = (u*P + t)*E .. +E-1 of a period, address
+(o // w)*m + o % w + k from the period start, list item c*W + (o + k) % w;
+the last row team adds the rows after the whole periods.  Every element of
+the rows x m block must be read exactly once, inside the block, by a slot
+whose list item is the element's column.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2106_03219_amd as om
+from paper_2106_03219_amd import _lib
+
+ESIZE = {om.I32: 4, om.I64: 8, om.F32: 4, om.F64: 8, om.BF16: 2}
+
+
+def acc_bytes(dt, op):
+    if dt in (om.F32, om.BF16):
+        return 8 if op == "sum" else 4
+    if dt == om.F64:
+        return 16 if op == "sum" else 8
+    return ESIZE[dt]
+
+
+def bal(n, p, t):
+    q, r = divmod(n, p)
+    lo = t * q + min(t, r)
+    return lo, lo + q + (1 if t < r else 0)
+
+
+def replay(rows, m, dt, plan):
+    W, R, tiles, rt, ng, vb, P, U = plan
+    esize = ESIZE[dt]
+    E = vb // esize
+    np_ = rows // R
+    hits = np.zeros(rows * m, dtype=np.int64)
+    for c in range(tiles):
+        c0 = c * W
+        wc = min(W, m - c0)
+        span = R * wc
+        o = ((np.arange(U)[:, None] * P + np.arange(P)[None, :]) * E).ravel()
+        o = o[o < span]
+        k = np.arange(E)
+        flat = (o[:, None] + k[None, :]).ravel()            # LDS index of every element
+        addr0 = ((o // wc) * m + o % wc)[:, None] + k[None, :]
+        addr0 = addr0.ravel()
+        item = c0 + flat % wc
+        assert flat.max() < span and np.unique(flat).size == flat.size
+        for r in range(rt):
+            lo, hi = bal(np_, rt, r)
+            for p in range(lo, hi):
+                a = c0 + p * R * m + addr0
+                assert a.min() >= 0 and a.max() < rows * m
+                assert np.array_equal(a % m, item)
+                np.add.at(hits, a, 1)
+            if r == rt - 1:
+                tl = (rows - np_ * R) * wc
+                ot = np.arange(U * P * E)
+                ot = ot[ot < tl]
+                a = c0 + np_ * R * m + (ot // wc) * m + ot % wc
+                if a.size:
+                    assert a.max() < rows * m
+                    assert np.array_equal(a % m, c0 + ot % wc)
+                np.add.at(hits, a, 1)
+    assert np.all(hits == 1)
+
+
+CASES = [(1, 1), (5, 1), (3, 7), (1000, 1), (1000, 3), (777, 8), (513, 100), (300, 256),
+         (300, 257), (97, 1000), (50, 1001), (40, 4096), (9, 5000), (3, 20000), (2000, 33)]
+
+
+@pytest.mark.parametrize("dt", [om.I32, om.I64, om.F32, om.F64, om.BF16])
+@pytest.mark.parametrize("aligned", [1, 0])
+def test_geometry_covers_every_element_once(dt, aligned):
+    for rows, m in CASES:
+        for op in ("sum", "max"):
+            plan = om.reduce_array_plan(rows, m, dt, op, aligned16=aligned)
+            W, R, tiles, rt, ng, vb, P, U = plan
+            E = vb // ESIZE[dt]
+            assert vb in (16, ESIZE[dt]) and (vb == 16) <= bool(aligned)
+            assert R * min(W, m) <= P * E * U
+            assert R * min(W, m) * acc_bytes(dt, op) <= 64 * 1024 - 256
+            assert tiles == -(-m // W) and W % E == 0 or tiles == 1
+            if tiles == 1:
+                assert W == m and (vb != 16 or (R * m * ESIZE[dt]) % 16 == 0)
+            else:
+                assert m % E == 0 and m - (tiles - 1) * W > 0
+            assert 1 <= rt <= max(1, rows // R)
+            gs = rt if rt <= 32 else 16
+            assert ng == -(-rt // gs)
+            replay(rows, m, dt, plan)
+
+
+def test_geometry_under_explicit_configs():
+    for cfg in [dict(threads=64, unroll=1), dict(threads=1024, unroll=1), dict(threads=128, unroll=8),
+                dict(threads=1024), dict(teams=3), dict(teams=65535), dict(vec=4)]:
+        for rows, m in [(1000, 3), (300, 257), (97, 1000), (64, 4096), (5000, 1)]:
+            plan = om.reduce_array_plan(rows, m, om.F32, "sum", config=cfg)
+            replay(rows, m, om.F32, plan)
+    # an explicit unroll whose private copies do not fit in LDS is an error
+    with pytest.raises(om.OmprtError):
+        om.reduce_array_plan(100, 100, om.F32, "sum", config=dict(threads=1024, unroll=8))
+
+
+def test_tiles_are_balanced():
+    W, R, tiles, *_ = om.reduce_array_plan(100, 257, om.F32, "sum", aligned16=False)
+    assert tiles == 2 and W == 129
+    W, R, tiles, *_ = om.reduce_array_plan(100, 1 << 20, om.F32, "sum")
+    assert W == 256 and tiles == 4096
+
+
+def test_argument_errors_before_device():
+    lib = _lib.load()
+    x = ctypes.c_float(0)
+    A = lib.omprt_reduce_array
+    assert A(None, 5, 5, 9, 0, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
+    assert A(None, 5, 5, 0, 3, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
+    assert A(None, -1, 5, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
+    assert A(None, 5, -1, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
+    assert A(None, 1 << 30, 1 << 30, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
+    assert A(None, 0, 5, 0, 0, None, None, None) == _lib.OK        # nothing to do
+    assert A(None, 5, 0, 0, 0, None, None, None) == _lib.OK
+    assert A(None, 5, 5, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID   # NULL in
+    assert A(ctypes.c_void_p(0x1002), 5, 5, 0, 0, ctypes.c_void_p(0x100000), None, None) == _lib.ERR_INVALID
+    assert A(ctypes.c_void_p(0x1000), 5, 5, 0, 0, ctypes.c_void_p(0x1010), None, None) == _lib.ERR_INVALID
+    assert b"overlaps" in lib.omprt_last_error()
+    c = _lib.Config(0, 100, 0, 0, 0, 0)
+    assert A(ctypes.c_void_p(0x1000), 5, 5, 0, 0, ctypes.c_void_p(0x100000), ctypes.byref(c), None) == _lib.ERR_INVALID
+    c = _lib.Config(0, 0, 8, 0, 0, 0)
+    assert A(ctypes.c_void_p(0x1000), 5, 5, 2, 0, ctypes.c_void_p(0x100000), ctypes.byref(c), None) == _lib.ERR_INVALID
+    c = _lib.Config(0, 0, 0, 3, 0, 0)
+    assert A(ctypes.c_void_p(0x1000), 5, 5, 2, 0, ctypes.c_void_p(0x100000), ctypes.byref(c), None) == _lib.ERR_INVALID
+    c = _lib.Config(70000, 0, 0, 0, 0, 0)
+    assert A(ctypes.c_void_p(0x1000), 5, 5, 2, 0, ctypes.c_void_p(0x100000), ctypes.byref(c), None) == _lib.ERR_INVALID
+    out = (ctypes.c_int64 * 8)()
+    assert lib.omprt_reduce_array_plan(0, 5, 0, 0, 1, None, out) == _lib.ERR_INVALID
+    assert lib.omprt_reduce_array_plan(5, 5, 0, 0, 1, None, None) == _lib.ERR_INVALID
