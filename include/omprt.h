@@ -179,14 +179,17 @@ omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
  * (whole, or cut into column tiles) keep that alignment, otherwise one
  * element per load.  The runtime cuts the block into column tiles and row
  * periods (omprt_reduce_array_plan); teams on one tile combine through
- * tagged slots and wrap-around-increment elections, in groups of 16.
+ * tagged slots and wrap-around-increment elections, in one or two levels
+ * of groups.
  * cfg (may be NULL): num_teams is the total team count aimed at (default
- * 2 per compute unit); threads_per_team 64..1024 in steps of 64 (default
- * 256); unroll 1, 2, 4 or 8 loads in flight per lane (default 4; at most
- * 4 with 16-byte loads).  A team's private copies (threads x unroll x
- * elements per load) must fit 64 KiB of LDS: the default unroll is lowered
- * until they do; with an explicit unroll the call falls back to element
- * loads, and is INVALID if even those do not fit.  vec_bytes 0 or
+ * one per compute unit, two with element loads); threads_per_team 64..512 in steps of 64 (default
+ * 512); unroll 1, 2, 4 or 8 loads in flight per lane (default 4 with
+ * 16-byte loads, which take at most 4; 8 with element loads).  A team
+ * gathers its private copies in LDS at the end: threads x unroll x elements
+ * per load of them, or threads x elements per load when each load layer
+ * holds whole rows of the tile; they must fit 64 KiB.  The default unroll
+ * is lowered until they do; with an explicit unroll the call falls back to
+ * element loads, and is INVALID if even those do not fit.  vec_bytes 0 or
  * 16 (vectors where possible) or the element size (one element per load).
  * The learned model and tuned cache are not consulted.
  * Errors: UNSUPPORTED for dtype/op out of range; INVALID for rows or m

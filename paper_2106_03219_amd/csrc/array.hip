@@ -15,11 +15,12 @@
 // Combination.  The private copies go to LDS as an R x w matrix whose rows
 // are folded pairwise (R -> ceil(R/2) -> ... -> 1).  With one row team per
 // tile the team writes x directly.  Otherwise each team publishes its w
-// partials as tagged slot words; teams are grouped (16 per group) and the
-// wrap-around increment elects the last team of each group, which folds its
-// group's partials in team order; with more than one group the group results
-// are published and the last group of the tile folds them and writes x.  The
-// last tile to finish advances the launch epoch.
+// partials as tagged slot words; the row teams of a tile form election
+// groups, sized so that the last team of a group folds the group's rows
+// with at most 16 partials per thread, and the wrap-around increment elects
+// that last team.  With one group it writes x; otherwise the group results
+// are published and the last group of the tile folds them and writes x.
+// The last tile to finish advances the launch epoch.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -27,6 +28,7 @@
 #include "device.h"
 #include "launch.h"
 #include "runtime.h"
+#include "stream.h"
 
 namespace omprt {
 
@@ -59,7 +61,7 @@ __device__ __forceinline__ typename R::Acc fold_tagged(const uint64_t* first, in
                                                        uint32_t* status) {
     using Acc = typename R::Acc;
     constexpr int NW = sizeof(Acc) / 4;
-    constexpr int kBatch = 8;
+    constexpr int kBatch = NW <= 2 ? 16 : 8;
     Acc a = R::identity();
     for (int q0 = 0; q0 < count; q0 += kBatch) {
         // unconditional loads (a batch past the end re-reads the last
@@ -103,43 +105,85 @@ __device__ __forceinline__ bool elect_last(uint32_t* counter, uint32_t e, int* s
     return *s_flag != 0;
 }
 
-template <int DT, int E>
-struct ArrayLoad;
+// Fold the rows of the LDS matrix [nrows][wc] pairwise into row 0
+// (nrows -> ceil(nrows / 2) -> ... -> 1).  Team-wide; ends with a barrier.
+template <class R>
+__device__ __forceinline__ void fold_rows(typename R::Acc* lds, int64_t nrows, int64_t wc) {
+    const int P = blockDim.x;
+    for (int64_t h = nrows; h > 1;) {
+        const int64_t half = (h + 1) / 2;
+        const int64_t cnt = (h - half) * wc;
+        for (int64_t i = threadIdx.x; i < cnt; i += P) lds[i] = R::combine(lds[i], lds[i + half * wc]);
+        __syncthreads();
+        h = half;
+    }
+}
+
+// The last team of a group folds the group's `count` published rows of wc
+// partials (row q at first + q * stride words, column j at + j * NW) into
+// lds[0 .. wc).  With fewer columns than threads, tpc = P / wc threads share
+// a column: thread (q0, j) folds rows q0, q0 + tpc, ... in order, and the
+// tpc results are folded pairwise in LDS.  Team-wide; ends with a barrier.
+// lds must hold max(P, wc) entries.
+template <class R>
+__device__ __forceinline__ void fold_group(const uint64_t* first, int64_t stride, int count,
+                                           int64_t wc, uint32_t tag, uint32_t* status,
+                                           typename R::Acc* lds) {
+    constexpr int NW = sizeof(typename R::Acc) / 4;
+    const int P = blockDim.x, t = threadIdx.x;
+    if (wc * 2 > P) {
+        for (int64_t j = t; j < wc; j += P)
+            lds[j] = fold_tagged<R>(first + j * NW, stride, count, tag, status);
+        __syncthreads();
+        return;
+    }
+    const int tpc = (int)(P / wc) < count ? (int)(P / wc) : count;
+    const int q0 = t / (int)wc, j = t % (int)wc;
+    if (q0 < tpc)
+        lds[(int64_t)q0 * wc + j] = fold_tagged<R>(first + q0 * stride + j * NW, stride * tpc,
+                                                   (count - q0 + tpc - 1) / tpc, tag, status);
+    __syncthreads();
+    fold_rows<R>(lds, tpc, wc);
+}
+
+// Loads of the streaming loop: one 16-byte vector (stream.h) or one element.
+template <int DT, bool VEC>
+struct ArrayLoad {
+    using L = VecLoad<DT, 16>;
+    using S = typename DType<DT>::S;
+    using T = typename L::T;
+    static constexpr int E = L::PER;
+    static __device__ __forceinline__ T load(const S* p) {
+        return L::load(reinterpret_cast<const T*>(p));
+    }
+    template <class R>
+    static __device__ __forceinline__ void fold(typename R::Acc* acc, const T& v) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) R::elem(acc[k], L::get(v, k));
+    }
+};
 template <int DT>
-struct ArrayLoad<DT, 1> {   // one element per load
+struct ArrayLoad<DT, false> {
     using S = typename DType<DT>::S;
     using T = S;
+    static constexpr int E = 1;
     static __device__ __forceinline__ T load(const S* p) { return __builtin_nontemporal_load(p); }
     template <class R>
     static __device__ __forceinline__ void fold(typename R::Acc* acc, const T& v) {
         R::elem(acc[0], DType<DT>::from(v));
     }
 };
-template <int DT, int E>
-struct ArrayLoad {   // one 16-byte vector of E elements per load
-    using S = typename DType<DT>::S;
-    using T = u32x4;
-    static __device__ __forceinline__ T load(const S* p) {
-        return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
-    }
-    template <class R>
-    static __device__ __forceinline__ void fold(typename R::Acc* acc, const T& v) {
-        uint32_t w[4] = {v[0], v[1], v[2], v[3]};
-#pragma unroll
-        for (int k = 0; k < E; ++k) R::elem(acc[k], DType<DT>::at(w, k));
-    }
-};
 
 template <int DT, int OP, bool VEC, int U>
-__global__ __launch_bounds__(1024) void array_reduce_kernel(
+__global__ __launch_bounds__(512) void array_reduce_kernel(
     const typename DType<DT>::S* __restrict__ in, typename Red<DT, OP>::Out* __restrict__ x,
     ArrayGeom g, ArrayCross ct) {
     using D = DType<DT>;
     using R = Red<DT, OP>;
     using Acc = typename R::Acc;
     using S = typename D::S;
-    constexpr int E = VEC ? 16 / (int)sizeof(S) : 1;
-    using Ld = ArrayLoad<DT, E>;
+    using Ld = ArrayLoad<DT, VEC>;
+    constexpr int E = Ld::E;
     constexpr int NW = sizeof(Acc) / 4;
 
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -196,22 +240,32 @@ __global__ __launch_bounds__(1024) void array_reduce_kernel(
         }
     }
 
-    // private copies -> LDS as [R][wc]; fold the rows pairwise
+    // Private copies -> LDS as a [rows][wc] matrix, whose rows are then
+    // folded pairwise.  When every slot of a period is live and one layer of
+    // P * E offsets holds whole rows, a lane's U slots are copies of the same
+    // list items: they fold in registers first and LDS holds P * E / wc rows.
+    const int64_t layer = (int64_t)P * E;
+    const bool fold_u = U > 1 && span == U * layer && layer % wc == 0;
+    int64_t nrows = g.R;
+    if (fold_u) {
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+        for (int u = 1; u < U; ++u)
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-            const int64_t o = ((int64_t)u * P + tid) * E + k;
-            if (o < span) lds[o] = acc[u][k];
-        }
-    __syncthreads();
-    for (int64_t h = g.R; h > 1;) {
-        const int64_t half = (h + 1) / 2;
-        const int64_t cnt = (h - half) * wc;
-        for (int64_t i = tid; i < cnt; i += P) lds[i] = R::combine(lds[i], lds[i + half * wc]);
-        __syncthreads();
-        h = half;
+            for (int k = 0; k < E; ++k) acc[0][k] = R::combine(acc[0][k], acc[u][k]);
+#pragma unroll
+        for (int k = 0; k < E; ++k) lds[(int64_t)tid * E + k] = acc[0][k];
+        nrows = layer / wc;
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int64_t o = ((int64_t)u * P + tid) * E + k;
+                if (o < span) lds[o] = acc[u][k];
+            }
     }
+    __syncthreads();
+    fold_rows<R>(lds, nrows, wc);
 
     if (!cross) {
         for (int64_t j = tid; j < wc; j += P) x[c0 + j] = R::finish(lds[j], x[c0 + j]);
@@ -227,22 +281,18 @@ __global__ __launch_bounds__(1024) void array_reduce_kernel(
     if (!elect_last(ct.counters + (int64_t)c * g.ng + grp, (uint32_t)(gsz - 1), &s_last)) return;
 
     const int64_t stride = g.m * NW;
-    for (int64_t j = tid; j < wc; j += P) {
-        const Acc a = fold_tagged<R>(ct.slots1 + ((int64_t)first * g.m + c0 + j) * NW, stride, gsz,
-                                     tag, ct.status);
-        if (g.ng == 1)
-            x[c0 + j] = R::finish(a, x[c0 + j]);
-        else
-            publish_tagged(a, ct.slots2 + ((int64_t)grp * g.m + c0 + j) * NW, tag);
-    }
-    if (g.ng > 1) {
+    fold_group<R>(ct.slots1 + ((int64_t)first * g.m + c0) * NW, stride, gsz, wc, tag, ct.status,
+                  lds);
+    if (g.ng == 1) {
+        for (int64_t j = tid; j < wc; j += P) x[c0 + j] = R::finish(lds[j], x[c0 + j]);
+    } else {
+        for (int64_t j = tid; j < wc; j += P)
+            publish_tagged(lds[j], ct.slots2 + ((int64_t)grp * g.m + c0 + j) * NW, tag);
         if (!elect_last(ct.counters + (int64_t)g.col_tiles * g.ng + c, (uint32_t)(g.ng - 1),
                         &s_last))
             return;
-        for (int64_t j = tid; j < wc; j += P) {
-            const Acc a = fold_tagged<R>(ct.slots2 + (c0 + j) * NW, stride, g.ng, tag, ct.status);
-            x[c0 + j] = R::finish(a, x[c0 + j]);
-        }
+        fold_group<R>(ct.slots2 + c0 * NW, stride, g.ng, wc, tag, ct.status, lds);
+        for (int64_t j = tid; j < wc; j += P) x[c0 + j] = R::finish(lds[j], x[c0 + j]);
     }
     // the tile is done; the last tile advances the epoch (every team of the
     // launch read it before publishing)
@@ -268,7 +318,7 @@ static void launch_array_one(const void* in, void* x, const ArrayGeom& g, const 
 }
 
 // Element loads: unroll 1..8.  16-byte loads: unroll 1..4 (eight vectors of
-// private copies per lane would not fit the registers of a 1024-thread team).
+// private copies per lane would crowd out the registers).
 template <int DT, int OP>
 static ArrayLauncher array_pick_v(bool vec, int u) {
     switch (u) {
@@ -394,7 +444,7 @@ omprt_status array_reset(int dev, hipStream_t stream) {
 // ---------------------------------------------------------------- planning
 
 constexpr int64_t kTileCols = 256;      // target tile width when rows are wider
-constexpr int kGroup = 16;              // teams per election group
+constexpr int64_t kFoldItems = 16;     // partials one thread folds per election level
 constexpr int kMaxLdsBytes = 64 * 1024 - 256;   // dynamic LDS; the rest is static
 
 static int64_t gcd64(int64_t a, int64_t b) {
@@ -426,6 +476,21 @@ static bool array_geometry(int64_t rows, int64_t m, int E, int64_t L, ArrayGeom*
     return true;
 }
 
+// LDS entries a team needs for its private copies: the span of a period,
+// or one layer of P * E offsets when the kernel folds the U slots of a lane
+// in registers (every slot live, whole rows per layer).  Maximum over the
+// full tiles and the last one.
+static int64_t lds_entries(const ArrayGeom& g, int64_t layer, int U) {
+    const int64_t wl = g.m - (int64_t)(g.col_tiles - 1) * g.W;
+    int64_t need = 0;
+    for (int64_t wc : {std::min(g.W, g.m), wl}) {
+        const int64_t span = g.R * wc;
+        const bool fold = U > 1 && span == U * layer && layer % wc == 0;
+        need = std::max(need, fold ? layer : span);
+    }
+    return need;
+}
+
 struct ArrayPlan {
     ArrayGeom g;
     bool vec;
@@ -437,11 +502,11 @@ static omprt_status plan_array(int64_t rows, int64_t m, int dtype, int op, const
                                const omprt_config* cfg, ArrayPlan* out) {
     const int esize = dtype_bytes(dtype);
     const int ab = acc_bytes(dtype, op);
-    int P = 256, U = 4, want_teams = 2 * device_cus();
+    int P = 512, U = 4, want_teams = 0;
     bool allow_vec = true;
     if (cfg) {
         if (cfg->threads_per_team) {
-            if (cfg->threads_per_team < 64 || cfg->threads_per_team > 1024 ||
+            if (cfg->threads_per_team < 64 || cfg->threads_per_team > 512 ||
                 cfg->threads_per_team % 64)
                 return fail(OMPRT_ERR_INVALID, "threads_per_team %d", cfg->threads_per_team);
             P = cfg->threads_per_team;
@@ -467,32 +532,49 @@ static omprt_status plan_array(int64_t rows, int64_t m, int dtype, int op, const
     ArrayPlan pl{};
     pl.threads = P;
     bool found = false;
+    // 16-byte loads first, then element loads; the default unroll is lowered
+    // until the private copies fit LDS, an explicit one is kept or dropped.
     for (int pass = allow_vec ? 0 : 1; pass < 2 && !found; ++pass) {
         const bool vec = pass == 0;
         if (vec && (reinterpret_cast<uintptr_t>(in) & 15)) continue;
         const int E = vec ? 16 / esize : 1;
-        int u = vec ? std::min(U, 4) : U;
-        while ((int64_t)P * E * u * ab > kMaxLdsBytes && u > 1 && !explicit_u) u /= 2;
-        if ((int64_t)P * E * u * ab > kMaxLdsBytes) {
-            if (!vec)
-                return fail(OMPRT_ERR_INVALID,
-                            "threads %d x unroll %d needs more than %d bytes of LDS", P, u,
-                            kMaxLdsBytes);
-            continue;   // element loads need E times less
+        const int u0 = vec ? std::min(U, 4) : (explicit_u ? U : 8);   // element loads: 8 in flight
+        for (int u = u0; u >= 1 && !found; u /= 2) {
+            ArrayGeom g{};
+            if (array_geometry(rows, m, E, (int64_t)P * E * u, &g)) {
+                // the group fold also needs one entry per thread
+                const size_t bytes =
+                    (size_t)std::max<int64_t>(lds_entries(g, (int64_t)P * E, u), P) * ab;
+                if (bytes <= (size_t)kMaxLdsBytes) {
+                    pl.g = g;
+                    pl.vec = vec;
+                    pl.unroll = u;
+                    pl.lds = bytes;
+                    found = true;
+                }
+            }
+            if (explicit_u) break;
         }
-        if (!array_geometry(rows, m, E, (int64_t)P * E * u, &pl.g)) continue;
-        pl.vec = vec;
-        pl.unroll = u;
-        found = true;
     }
-    if (!found) return fail(OMPRT_ERR_INVALID, "no array geometry (threads %d)", P);
+    if (!found)
+        return fail(OMPRT_ERR_INVALID,
+                    "no launch geometry: the private copies of threads %d x unroll %d do not "
+                    "fit %d bytes of LDS", P, U, kMaxLdsBytes);
     ArrayGeom& g = pl.g;
+    // default: one team per compute unit with 16-byte loads, two with element
+    // loads (which keep a quarter of the bytes in flight per lane or less)
+    if (!want_teams) want_teams = device_cus() * (pl.vec ? 1 : 2);
     int64_t rt = std::max<int64_t>(1, want_teams / g.col_tiles);
     rt = std::min<int64_t>(rt, std::max<int64_t>(1, g.np));
     g.rt = (int32_t)rt;
-    g.gs = rt <= 2 * kGroup ? (int32_t)rt : kGroup;
+    // Election groups: as many teams as the last one can fold with at most
+    // kFoldItems partials per thread (fold_group); one group when all fit.
+    const int64_t wc_max = std::min(g.W, m);
+    const int64_t per_col = wc_max * 2 > P ? 1 : P / wc_max;   // threads per column
+    const int64_t rounds = (wc_max + P - 1) / P;               // columns per thread
+    const int64_t gs_max = std::max<int64_t>(2, kFoldItems * per_col / rounds);
+    g.gs = (int32_t)std::min(rt, gs_max);
     g.ng = (int32_t)((rt + g.gs - 1) / g.gs);
-    pl.lds = (size_t)(g.R * std::min<int64_t>(g.W, m)) * ab;
     *out = pl;
     return OMPRT_OK;
 }

@@ -8,31 +8,50 @@
 
 namespace omprt {
 
-template <int VB>
-struct VecOf;
-template <>
-struct VecOf<16> {
-    using T = u32x4;
-    static constexpr int kDwords = 4;
+// One VB-byte load of elements of type DT: T is a vector of the element type
+// itself (loading a vector of dwords and rebuilding 64-bit elements from them
+// lets the compiler split the load), bfloat16 excepted: its halves come out
+// of dwords by shifts.
+template <class S, int N>
+struct VecType {
+    using T = S __attribute__((ext_vector_type(N)));
+    static __device__ __forceinline__ S get(const T& v, int k) { return v[k]; }
 };
-template <>
-struct VecOf<8> {
-    using T = u32x2;
-    static constexpr int kDwords = 2;
+template <class S>
+struct VecType<S, 1> {
+    using T = S;
+    static __device__ __forceinline__ S get(const T& v, int) { return v; }
+};
+
+template <int DT, int VB>
+struct VecLoad {
+    using S = typename DType<DT>::S;
+    static constexpr int PER = VB / (int)sizeof(S);   // elements per load
+    using VT = VecType<S, PER>;
+    using T = typename VT::T;
+    static __device__ __forceinline__ T load(const T* p) { return __builtin_nontemporal_load(p); }
+    static __device__ __forceinline__ typename DType<DT>::V get(const T& v, int k) {
+        return DType<DT>::from(VT::get(v, k));
+    }
+};
+template <int VB>
+struct VecLoad<DT_BF16, VB> {
+    static constexpr int PER = VB / 2;
+    using T = uint32_t __attribute__((ext_vector_type(VB / 4)));
+    static __device__ __forceinline__ T load(const T* p) { return __builtin_nontemporal_load(p); }
+    static __device__ __forceinline__ float get(const T& v, int k) {
+        const uint32_t d = v[k >> 1];
+        return __uint_as_float((k & 1) ? (d & 0xFFFF0000u) : (d << 16));
+    }
 };
 
 template <int DT, int OP, int VB>
 __device__ __forceinline__ void accumulate_vec(typename Red<DT, OP>::Acc* acc,
-                                               const typename VecOf<VB>::T& v) {
-    using D = DType<DT>;
+                                               const typename VecLoad<DT, VB>::T& v) {
     using R = Red<DT, OP>;
-    constexpr int DW = VecOf<VB>::kDwords;
-    constexpr int PER = D::kPerDword2 * DW / 2;
-    uint32_t w[DW];
+    using L = VecLoad<DT, VB>;
 #pragma unroll
-    for (int i = 0; i < DW; ++i) w[i] = v[i];
-#pragma unroll
-    for (int e = 0; e < PER; ++e) R::elem(acc[e % R::kNA], D::at(w, e));
+    for (int e = 0; e < L::PER; ++e) R::elem(acc[e % R::kNA], L::get(v, e));
 }
 
 // acc has Red<DT,OP>::kNA entries; every thread of the team calls this with
@@ -44,8 +63,9 @@ __device__ __forceinline__ void stream_range(const typename DType<DT>::S* __rest
     using D = DType<DT>;
     using R = Red<DT, OP>;
     using S = typename D::S;
-    using Vec = typename VecOf<VB>::T;
-    constexpr int PER = D::kPerDword2 * VecOf<VB>::kDwords / 2;   // elements per vector
+    using L = VecLoad<DT, VB>;
+    using Vec = typename L::T;
+    constexpr int PER = L::PER;   // elements per vector
     if (a >= b) return;
     const int tid = threadIdx.x;
     const int P = blockDim.x;
@@ -60,12 +80,12 @@ __device__ __forceinline__ void stream_range(const typename DType<DT>::S* __rest
     for (; v + (int64_t)(U - 1) * P < nv; v += (int64_t)U * P) {
         Vec r[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) r[u] = __builtin_nontemporal_load(vp + v + (int64_t)u * P);
+        for (int u = 0; u < U; ++u) r[u] = L::load(vp + v + (int64_t)u * P);
 #pragma unroll
         for (int u = 0; u < U; ++u) accumulate_vec<DT, OP, VB>(acc, r[u]);
     }
     for (; v < nv; v += P) {
-        const Vec r = __builtin_nontemporal_load(vp + v);
+        const Vec r = L::load(vp + v);
         accumulate_vec<DT, OP, VB>(acc, r);
     }
     const int64_t t0 = p0 + nv * PER;

@@ -28,6 +28,17 @@ def acc_bytes(dt, op):
     return ESIZE[dt]
 
 
+def lds_entries(R, W, m, tiles, layer, U):
+    """Private copies a team gathers in LDS: a period's span, or one layer of
+    P*E offsets when all U layers are live and each holds whole tile rows."""
+    need = 0
+    for wc in (min(W, m), m - (tiles - 1) * W):
+        span = R * wc
+        fold = U > 1 and span == U * layer and layer % wc == 0
+        need = max(need, layer if fold else span)
+    return need
+
+
 def bal(n, p, t):
     q, r = divmod(n, p)
     lo = t * q + min(t, r)
@@ -85,27 +96,34 @@ def test_geometry_covers_every_element_once(dt, aligned):
             E = vb // ESIZE[dt]
             assert vb in (16, ESIZE[dt]) and (vb == 16) <= bool(aligned)
             assert R * min(W, m) <= P * E * U
-            assert R * min(W, m) * acc_bytes(dt, op) <= 64 * 1024 - 256
+            assert lds_entries(R, W, m, tiles, P * E, U) * acc_bytes(dt, op) <= 64 * 1024 - 256
             assert tiles == -(-m // W) and W % E == 0 or tiles == 1
             if tiles == 1:
                 assert W == m and (vb != 16 or (R * m * ESIZE[dt]) % 16 == 0)
             else:
                 assert m % E == 0 and m - (tiles - 1) * W > 0
             assert 1 <= rt <= max(1, rows // R)
-            gs = rt if rt <= 32 else 16
+            wc = min(W, m)
+            per_col = 1 if wc * 2 > P else P // wc
+            gs = min(rt, max(2, 16 * per_col // -(-wc // P)))
             assert ng == -(-rt // gs)
             replay(rows, m, dt, plan)
 
 
 def test_geometry_under_explicit_configs():
-    for cfg in [dict(threads=64, unroll=1), dict(threads=1024, unroll=1), dict(threads=128, unroll=8),
-                dict(threads=1024), dict(teams=3), dict(teams=65535), dict(vec=4)]:
+    for cfg in [dict(threads=64, unroll=1), dict(threads=512, unroll=1), dict(threads=128, unroll=8),
+                dict(threads=512), dict(teams=3), dict(teams=65535), dict(vec=4)]:
         for rows, m in [(1000, 3), (300, 257), (97, 1000), (64, 4096), (5000, 1)]:
             plan = om.reduce_array_plan(rows, m, om.F32, "sum", config=cfg)
             replay(rows, m, om.F32, plan)
-    # an explicit unroll whose private copies do not fit in LDS is an error
+    # teams of more than 512 threads are refused; an explicit unroll whose
+    # private copies fit LDS only with element loads falls back to them
     with pytest.raises(om.OmprtError):
-        om.reduce_array_plan(100, 100, om.F32, "sum", config=dict(threads=1024, unroll=8))
+        om.reduce_array_plan(100, 100, om.F32, "sum", config=dict(threads=1024))
+    assert om.reduce_array_plan(100, 100, om.BF16, "sum", config=dict(threads=512, unroll=4))[5] == 2
+    # whole rows in every layer: the lane's slots fold in registers, so
+    # 512 threads x 4 loads of fp32 sums fit
+    assert om.reduce_array_plan(1 << 20, 8, om.F32, "sum", config=dict(threads=512))[7] == 4
 
 
 def test_tiles_are_balanced():

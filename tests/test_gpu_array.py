@@ -87,7 +87,7 @@ def test_ragged_shapes_default_launch(gpu_lib, dtype, op):
 
 
 CONFIGS = [{"vec": 0}, {"teams": 1}, {"teams": 3}, {"teams": 4096}, {"threads": 64, "unroll": 1},
-           {"threads": 1024, "unroll": 1}, {"threads": 128, "unroll": 8}]
+           {"threads": 512, "unroll": 1}, {"threads": 256, "teams": 512}, {"threads": 128, "unroll": 8}]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -135,6 +135,18 @@ def test_two_level_groups_repeated_launches_identical(gpu_lib):
     # int64 sums over the same groups are exact
     hi = synth.host(synth.I64, rows * m, 4001).reshape(rows, m)
     run_and_check(om, hi, synth.I64, "sum", np.zeros(m, np.int64), config={"teams": 4096})
+
+
+@pytest.mark.parametrize("rows,m,cfg", [((1 << 14) + 77, 1024, {"threads": 256, "teams": 4096}),
+                                        ((1 << 17) + 5, 300, {"teams": 4096})])
+def test_two_level_groups_wide_rows(gpu_lib, rows, m, cfg):
+    om = gpu_lib
+    plan = om.reduce_array_plan(rows, m, synth.F32, "sum", config=cfg)
+    assert plan[2] > 1 and plan[4] > 1       # column tiles, each with several election groups
+    for dtype in (synth.F32, synth.I64):
+        host = synth.host(dtype, rows * m, 4100 + m).reshape(rows, m)
+        run_and_check(om, host, dtype, "sum", x_init(dtype, "sum", m, 9), config=cfg)
+    assert om.workspace_status() == 0
 
 
 def test_empty_and_unchanged(gpu_lib):
