@@ -9,8 +9,9 @@ dominant kernel (the int64 sum, timed with HIP events on its stream over
 the timed region), and the CPU baseline leg: the oracle timed on the host over
 the same step, whose results also check the GPU step.  Unless --no-extras:
 the AXPY worksharing body, launch latency, the 4096-segment batched workload
-(plain launches vs one graph-replayed persistent launch) and the learned
-picker against the heuristic on held-out instances.
+(plain launches vs one graph-replayed persistent launch), device atomics,
+array-section reductions, and the learned picker against the heuristic on
+held-out instances.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -314,6 +315,46 @@ def bench_atomics(om, torch):
     return {"ops": n, "gops_per_s": out}
 
 
+def bench_array(om, torch):
+    """Array-section reductions reduction(+: x[0:m]) over 2^28-element row-major blocks
+    (1 GiB fp32, 2 GiB int64) in the runtime's default launch: GB/s of the input read
+    per launch, the same data's plain reduction for scale, and a check of every column
+    against torch's column sums (int64 exact, fp32 within 1e-6 of an fp64 sum)."""
+    _log("array-section reductions")
+    out = []
+    n = 1 << 28
+    for rows, m, dt in ((n // 8, 8, torch.float32), (n // 4096, 4096, torch.float32),
+                        (n >> 20, 1 << 20, torch.float32), (n // 8, 8, torch.int64)):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(90 + m)
+        if dt == torch.int64:
+            inp = torch.randint(-(2**40), 2**40, (n,), device="cuda", dtype=dt, generator=g)
+        else:
+            inp = torch.randn(n, device="cuda", dtype=dt, generator=g)
+        x = torch.zeros(m, dtype=dt, device="cuda")
+        us = _time_us(lambda: om.reduce_array(inp, rows, m, "sum", x), torch, reps=5)
+        xs = torch.zeros(1, dtype=dt, device="cuda")
+        us_plain = _time_us(lambda: om.reduce(inp, "sum", xs), torch, reps=5)
+        x.zero_()
+        om.reduce_array(inp, rows, m, "sum", x)
+        ref = inp.view(rows, m).sum(dim=0, dtype=torch.float64 if dt == torch.float32 else dt)
+        if dt == torch.int64:
+            ok = bool(torch.equal(x, ref))
+        else:
+            ok = bool(((x.double() - ref).abs() <= 1e-6 * ref.abs() + 1e-6).all())
+        plan = om.reduce_array_plan(rows, m, om.dtype_code(inp), "sum")
+        out.append({"rows": rows, "m": m, "dtype": str(dt).replace("torch.", ""),
+                    "us": round(us, 1), "gb_per_s": round(n * inp.element_size() / us / 1e3, 1),
+                    "plain_reduction_gb_per_s": round(n * inp.element_size() / us_plain / 1e3, 1),
+                    "tiles": plan[2], "row_teams": plan[3], "groups": plan[4], "columns_ok": ok})
+        if not ok:
+            _log(f"ARRAY COLUMN MISMATCH rows={rows} m={m} {dt}")
+            sys.exit(1)
+        del inp, ref
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_learned(om, torch, count=300):
     """The learned picker on a sample of the held-out instance distribution (seed 8,
     n <= 1e8): total and geometric-mean time with the model's launches vs the built-in
@@ -385,12 +426,14 @@ def main():
     ap.add_argument("--cpu-passes", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the AXPY, launch-latency and batched measurements")
+                    help="skip the AXPY, latency, batched, atomics, array and picker measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 3 device copies of 2^28 fp32 (1 GiB read + 1 GiB written), "
                          "the reference for scaling HBM byte counters")
     ap.add_argument("--only-axpy", type=int, nargs=2, metavar=("TEAMS", "CHUNK"), default=None,
                     help="only run 3 AXPY+sum launches over 2^26 with 256 threads (profiling)")
+    ap.add_argument("--only-array", action="store_true",
+                    help="only run the array-section reduction measurements (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -415,6 +458,10 @@ def main():
             om.axpy_sum(0.7, x, y, s, teams, 256, 0, chunk)
         torch.cuda.synchronize()
         _log(f"3 AXPY+sum launches over 2^26, {teams} teams x 256 threads, chunk {chunk}")
+        return
+
+    if args.only_array:
+        print(json.dumps({"array_reduction": bench_array(om, torch)}), flush=True)
         return
 
     if args.calibrate_copy:
@@ -492,6 +539,7 @@ def main():
         extra["latency"] = bench_latency(om, torch)
         extra["batched"] = bench_batched(om, torch)
         extra["atomics"] = bench_atomics(om, torch)
+        extra["array_reduction"] = bench_array(om, torch)
         learned = bench_learned(om, torch)
         if learned is not None:
             extra["learned_picker_heldout"] = learned
