@@ -14,6 +14,8 @@ statement of each):
   one team is one GPU thread block).
 * :func:`reduce_int`, :func:`reduce_fp` -- ``reduction(op:x)`` results:
   integer wrap arithmetic, FP64 Neumaier sums, fmax/fmin folds.
+* :func:`queue_chunks`, :func:`team_queue` -- dynamic / guided worksharing:
+  the chunks each distribute block's queue hands out (owners undefined).
 * :func:`axpy_sum` -- the AXPY worksharing body with fused fmaf.
 * :func:`atomic_serial` -- the five device atomics (sec. 3.1) applied in
   index order.
@@ -76,6 +78,10 @@ def _load():
     lib.oracle_adam.restype = None
     lib.oracle_atomic_serial.argtypes = [ctypes.c_int, p, i64, p, p, p, p, i64]
     lib.oracle_atomic_serial.restype = i64
+    lib.oracle_queue_chunks.argtypes = [ctypes.c_int, i64, i64, i64, p, p, i64]
+    lib.oracle_queue_chunks.restype = i64
+    lib.oracle_team_queue.argtypes = [ctypes.c_int, i64, i64, i64, i64, i64, i64, p, p, i64]
+    lib.oracle_team_queue.restype = i64
     _lib = lib
     return lib
 
@@ -214,3 +220,32 @@ def reduce_array(a2d, op, x, bf16=False):
         else:
             out.append(reduce_fp(col, op, x[j], bf16=bf16))
     return out
+
+
+QUEUE_KINDS = {"dynamic": 0, "guided": 1}
+
+
+def queue_chunks(kind, m, P, c):
+    """Chunks [lo, hi) (offsets in a block of m iterations) of schedule(kind, c), in order."""
+    lib = _load()
+    k = QUEUE_KINDS[kind]
+    cnt = lib.oracle_queue_chunks(k, m, P, c, None, None, 0)
+    if cnt < 0:
+        raise ValueError("invalid schedule arguments")
+    lo = np.zeros(max(cnt, 1), dtype=np.int64)
+    hi = np.zeros(max(cnt, 1), dtype=np.int64)
+    lib.oracle_queue_chunks(k, m, P, c, _ptr(lo), _ptr(hi), cnt)
+    return [(int(lo[i]), int(hi[i])) for i in range(cnt)]
+
+
+def team_queue(kind, n, T, P, dc, c, team):
+    """Absolute chunks team `team`'s queues hand out, block by block, in order."""
+    lib = _load()
+    k = QUEUE_KINDS[kind]
+    cnt = lib.oracle_team_queue(k, n, T, P, dc, c, team, None, None, 0)
+    if cnt < 0:
+        raise ValueError("invalid schedule arguments")
+    lo = np.zeros(max(cnt, 1), dtype=np.int64)
+    hi = np.zeros(max(cnt, 1), dtype=np.int64)
+    lib.oracle_team_queue(k, n, T, P, dc, c, team, _ptr(lo), _ptr(hi), cnt)
+    return [(int(lo[i]), int(hi[i])) for i in range(cnt)]

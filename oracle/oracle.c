@@ -30,6 +30,10 @@
  *  - AXPY worksharing body: y[i] <- fmaf(a, x[i], y[i]) (one rounding), then
  *    the sum over the updated y in FP64 Neumaier.
  *
+ *  - Dynamic and guided worksharing: the queue of chunks each distribute
+ *    block hands out (dynamic: fixed size; guided: ceil(remaining / P), at
+ *    least the chunk size).  Only the chunks are defined, not their owners.
+ *
  *  - Learned-configuration extension (not in the paper): a
  *    F -> H1 -> H2 -> K ReLU multilayer perceptron with softmax
  *    cross-entropy, its analytic backward pass and one Adam step
@@ -174,6 +178,79 @@ int64_t oracle_thread_chunks(int64_t n, int64_t T, int64_t P, int64_t dc,
         thread_chunks(tl[jt], th[jt], P, c, t, l, h, nth);
         for (int64_t q = 0; q < nth; q++) {
             if (total < cap) { lo[total] = l[q]; hi[total] = h[q]; }
+            total++;
+        }
+        free(l); free(h);
+    }
+    free(tl); free(th);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dynamic and guided worksharing                                           */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * schedule(dynamic[, c]) and schedule(guided[, c]) hand a team block of m
+ * iterations out as a queue of chunks, each taken by whichever thread asks
+ * next, so which thread runs a chunk is not defined -- only the chunks
+ * are.  (The paper lists worksharing loops among the routines the device
+ * runtime provides, sec. 1; the chunk rules are OpenMP's, read as below.)
+ *
+ *  - dynamic: chunks of c iterations in order, the last one shorter
+ *    (c == 0 means 1);
+ *  - guided: the next chunk takes ceil(r / P) of the r iterations not yet
+ *    handed out, but at least c (c == 0 means 1) and at most r.
+ *
+ * Writes the chunks of one block, as offsets [lo, hi) from its start, in
+ * queue order (at most cap of them) and returns how many there are, or -1
+ * for bad arguments.  kind: 0 dynamic, 1 guided.
+ */
+int64_t oracle_queue_chunks(int kind, int64_t m, int64_t P, int64_t c,
+                            int64_t *lo, int64_t *hi, int64_t cap)
+{
+    if (m < 0 || P < 1 || c < 0 || (kind != 0 && kind != 1)) return -1;
+    int64_t cmin = c > 0 ? c : 1;
+    int64_t start = 0, cnt = 0;
+    while (start < m) {
+        int64_t rest = m - start;
+        int64_t size = cmin;
+        if (kind == 1) {
+            int64_t share = (rest + P - 1) / P;   /* ceil(rest / P) */
+            if (share > size) size = share;
+        }
+        if (size > rest) size = rest;
+        if (cnt < cap) { lo[cnt] = start; hi[cnt] = start + size; }
+        cnt++;
+        start += size;
+    }
+    return cnt;
+}
+
+/*
+ * distribute [dist_schedule(static[, dc])] parallel for schedule(kind[, c])
+ * over n iterations with T teams of P threads: the chunks team k's queues
+ * hand out, block by block (each distribute block has a queue of its own),
+ * as absolute iteration ranges.  Writes at most cap chunks and returns the
+ * total, or -1 for bad arguments.
+ */
+int64_t oracle_team_queue(int kind, int64_t n, int64_t T, int64_t P, int64_t dc,
+                          int64_t c, int64_t k, int64_t *lo, int64_t *hi, int64_t cap)
+{
+    if (n < 0 || T < 1 || P < 1 || dc < 0 || c < 0 || k < 0 || k >= T) return -1;
+    int64_t ntc = team_chunks(n, T, dc, k, NULL, NULL, 0);
+    int64_t *tl = malloc(sizeof(int64_t) * (size_t)(ntc ? ntc : 1));
+    int64_t *th = malloc(sizeof(int64_t) * (size_t)(ntc ? ntc : 1));
+    team_chunks(n, T, dc, k, tl, th, ntc);
+    int64_t total = 0;
+    for (int64_t jt = 0; jt < ntc; jt++) {
+        int64_t m = th[jt] - tl[jt];
+        int64_t nq = oracle_queue_chunks(kind, m, P, c, NULL, NULL, 0);
+        int64_t *l = malloc(sizeof(int64_t) * (size_t)(nq ? nq : 1));
+        int64_t *h = malloc(sizeof(int64_t) * (size_t)(nq ? nq : 1));
+        oracle_queue_chunks(kind, m, P, c, l, h, nq);
+        for (int64_t q = 0; q < nq; q++) {
+            if (total < cap) { lo[total] = tl[jt] + l[q]; hi[total] = tl[jt] + h[q]; }
             total++;
         }
         free(l); free(h);
