@@ -242,6 +242,64 @@ omprt_status omprt_axpy_sum(float a, const float *d_x, float *d_y,
                             float *d_sum, const omprt_sched *s,
                             const omprt_config *cfg, void *hip_stream);
 
+/* ----------------------------------------------------------------------- */
+/* Dynamic and guided worksharing                                          */
+/* ----------------------------------------------------------------------- */
+
+/*
+ * schedule(dynamic[, c]) and schedule(guided[, c]) for the threads of a
+ * team (the distribute part stays static, as *s gives it).  Each distribute
+ * block of a team is handed out as a queue of chunks, one queue per block,
+ * in team-shared memory; threads take chunks as they ask, so which thread
+ * runs a chunk is not defined, only the chunks are (the paper lists the
+ * worksharing-loop routines among what the device runtime provides, sec. 1):
+ *   DYNAMIC: chunks of c iterations in order, the last one shorter;
+ *   GUIDED:  the next chunk takes ceil(r / P) of the r iterations left, at
+ *            least c and at most r.
+ * c = s->chunk, with 0 meaning 1; P = s->threads_per_team.
+ */
+typedef enum { OMPRT_SCHED_DYNAMIC = 1, OMPRT_SCHED_GUIDED = 2 } omprt_sched_kind;
+
+/*
+ * The j-th chunk (0-based) of one block of m iterations under kind, as
+ * offsets [*lb, *ub) from the block's start; *lb == *ub == m past the last
+ * chunk.  Host arithmetic (O(j) for guided).  INVALID for a bad kind, m
+ * outside 0..2^50, threads outside 1..1024, negative chunk or j, NULL
+ * outputs.
+ */
+omprt_status omprt_queue_chunk(int32_t kind, int64_t m, int32_t threads,
+                               int64_t chunk, int64_t j, int64_t *lb,
+                               int64_t *ub);
+
+/*
+ * Iteration map of *s under kind on the GPU: the thread that runs iteration
+ * i stores d_owner[i] = team * threads_per_team + thread and
+ * d_start[i] = the first iteration of i's chunk, and adds 1 to d_count[i]
+ * (the caller zeroes d_count).  tickets: chunks a thread takes per request
+ * (1..64).  num_teams and threads_per_team must be given.  Guided chunk
+ * bounds are computed on the host once per (block size, threads, chunk)
+ * and kept on the device until omprt_finalize (the first call for a block
+ * size must not be made while the stream is being captured).
+ * Verification kernel for the queue semantics.
+ */
+omprt_status omprt_queue_map(const omprt_sched *s, int32_t kind,
+                             int32_t tickets, int32_t *d_owner,
+                             uint32_t *d_count, int64_t *d_start,
+                             void *hip_stream);
+
+/*
+ * omprt_axpy_sum's body and sum (y[i] <- fmaf(a, x[i], y[i]); *d_sum +=
+ * sum of the updated y, compensated fp32) under kind instead of a static
+ * for-schedule.  s->num_teams / threads_per_team of 0: one team per compute
+ * unit / 512 threads.  Dynamic chunks of one iteration are taken four per
+ * request.  Guided tables as for omprt_queue_map.  y is bit-identical to the static schedules' result; the sum may
+ * differ in its last bits (the order of accumulation depends on which
+ * thread ran which chunk).
+ */
+omprt_status omprt_axpy_sum_queue(float a, const float *d_x, float *d_y,
+                                  float *d_sum, const omprt_sched *s,
+                                  int32_t kind, void *hip_stream);
+
 /*
  * An empty target region: one launch of s->num_teams teams in which every
  * thread computes its static-schedule bounds over s->n iterations and runs

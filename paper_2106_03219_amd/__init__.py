@@ -181,6 +181,35 @@ def axpy_sum(a, x, y, s, teams=0, threads=0, dist_chunk=0, chunk=0, config=None,
                                 _cfg(config), _stream(stream)), "axpy_sum")
 
 
+# ---------------------------------------------------------------- dynamic / guided
+
+SCHED_KINDS = {"dynamic": 1, "guided": 2}
+
+
+def queue_chunk(kind, m, threads, chunk, j):
+    """The j-th chunk [lo, hi) of a block of m iterations under schedule(kind, chunk)."""
+    lb, ub = ctypes.c_int64(), ctypes.c_int64()
+    check(load().omprt_queue_chunk(SCHED_KINDS[kind], int(m), int(threads), int(chunk), int(j),
+                                   ctypes.byref(lb), ctypes.byref(ub)), "queue_chunk")
+    return lb.value, ub.value
+
+
+def queue_map(kind, n, teams, threads, dist_chunk, chunk, owner, count, start, tickets=1,
+              stream=None):
+    """Iteration map under a dynamic / guided schedule (owner, count, chunk start)."""
+    sch = _sched(n, teams, threads, dist_chunk, chunk)
+    check(load().omprt_queue_map(ctypes.byref(sch), SCHED_KINDS[kind], int(tickets), _ptr(owner),
+                                 _ptr(count), _ptr(start), _stream(stream)), "queue_map")
+
+
+def axpy_sum_queue(kind, a, x, y, s, teams=0, threads=0, dist_chunk=0, chunk=0, stream=None):
+    """y <- fmaf(a, x, y) under a dynamic / guided schedule; s[0] += sum(updated y)."""
+    sch = _sched(x.numel(), teams, threads, dist_chunk, chunk)
+    check(load().omprt_axpy_sum_queue(ctypes.c_float(a), _ptr(x) if x.numel() else None,
+                                      _ptr(y) if y.numel() else None, _ptr(s), ctypes.byref(sch),
+                                      SCHED_KINDS[kind], _stream(stream)), "axpy_sum_queue")
+
+
 # ---------------------------------------------------------------- device atomics
 
 _ATOMICS = {"add": ATOMIC_ADD, "inc": ATOMIC_INC, "max": ATOMIC_MAX, "exchange": ATOMIC_EXCHANGE,

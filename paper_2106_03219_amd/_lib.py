@@ -57,6 +57,9 @@ SIGNATURES = {
     "omprt_axpy_sum": (_i32, [_f32, _p, _p, _p, _S, _C, _p]),
     "omprt_empty_region": (_i32, [_S, _p]),
     "omprt_atomic_apply": (_i32, [_i32, _p, _i64, _p, _p, _p, _p, _i64, _p]),
+    "omprt_queue_chunk": (_i32, [_i32, _i64, _i32, _i64, _i64, _p, _p]),
+    "omprt_queue_map": (_i32, [_S, _i32, _i32, _p, _p, _p, _p]),
+    "omprt_axpy_sum_queue": (_i32, [ctypes.c_float, _p, _p, _p, _S, _i32, _p]),
     "omprt_mlp_param_count": (_i64, [_D]),
     "omprt_mlp_forward": (_i32, [_D, _p, _p, _i32, _p, _p]),
     "omprt_mlp_loss_grad": (_i32, [_D, _p, _p, _p, _i32, _p, _p, _p]),

@@ -55,12 +55,18 @@ enum ConfigSource { kSrcExplicit = 0, kSrcModel = 1, kSrcTuned = 2, kSrcHeuristi
 omprt_status resolve_config(int64_t n, int dtype, int op, int body, int64_t chunk,
                             const omprt_config* cfg, LaunchCfg* out, int* source);
 
+// Validate a schedule (allow_auto: num_teams / threads_per_team may be 0).
+omprt_status check_sched(const omprt_sched* s, bool allow_auto);
+
 // Compute units of the current device (256 if it cannot be queried).
 int device_cus();
 
 // Batched plans (batched.hip): free everything; status word of a stream's plan.
 void batched_finalize();
 uint32_t* batched_status_word(int dev, hipStream_t stream);
+
+// Dynamic / guided worksharing (queue.hip): free the guided tables.
+void queue_finalize();
 
 // Array-section reductions (array.hip): free everything; status word of a
 // stream's workspace; re-zero its counters and status.

@@ -207,7 +207,7 @@ omprt_status resolve_config(int64_t n, int dtype, int op, int body, int64_t chun
 
 // ---------------------------------------------------------------- schedule checks
 
-static omprt_status check_sched(const omprt_sched* s, bool allow_auto) {
+omprt_status check_sched(const omprt_sched* s, bool allow_auto) {
     if (!s) return fail(OMPRT_ERR_INVALID, "schedule pointer is NULL");
     if (s->n < 0 || s->n > kMaxTrip)
         return fail(OMPRT_ERR_INVALID, "n = %lld outside 0..2^50", (long long)s->n);
@@ -516,6 +516,7 @@ extern "C" omprt_status omprt_finalize(void) {
     OMPRT_HIP(hipDeviceSynchronize());
     batched_finalize();
     array_finalize();
+    queue_finalize();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_ws) {
         if (!kv.second.base) continue;
