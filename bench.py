@@ -10,8 +10,8 @@ the timed region), and the CPU baseline leg: the oracle timed on the host over
 the same step, whose results also check the GPU step.  Unless --no-extras:
 the AXPY worksharing body, launch latency, the 4096-segment batched workload
 (plain launches vs one graph-replayed persistent launch), device atomics,
-array-section reductions, and the learned picker against the heuristic on
-held-out instances.
+array-section reductions, the AXPY body under dynamic / guided schedules, and
+the learned picker against the heuristic on held-out instances.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -132,6 +132,42 @@ def bench_axpy(om, torch):
             "runtime_choice_gb_s": round(12 * n / us / 1e3, 1),
             "y_identical_across_schedules": bool(same_y),
             "sum_spread_across_schedules": spread}
+
+
+def bench_queue(om, torch):
+    """The AXPY + sum body over 2^26 fp32 under schedule(dynamic, c) and schedule(guided,
+    c) for the threads of each team (distribute static, one team per compute unit, 512
+    threads), next to the static schedule with the same chunk.  y must be bit-identical to
+    the static schedule's and the sums within 2e-6 of it."""
+    import synth
+    _log("AXPY 2^26 under dynamic / guided schedules")
+    n = 1 << 26
+    x = synth.device(synth.F32, n, synth.SEED_AXPY_X)
+    y0 = synth.device(synth.F32, n, synth.SEED_AXPY_Y)
+    yref = y0.clone()
+    sref = torch.zeros(1, dtype=torch.float32, device="cuda")
+    om.axpy_sum(0.7, x, yref, sref)
+    torch.cuda.synchronize()
+    y = y0.clone()
+    s = torch.zeros(1, dtype=torch.float32, device="cuda")
+    out = {}
+    agree = True
+    for kind, c in (("static", 0), ("static", 1), ("static", 64), ("static", 1024),
+                    ("dynamic", 1), ("dynamic", 4), ("dynamic", 64), ("dynamic", 1024),
+                    ("guided", 1), ("guided", 64)):
+        if kind == "static":
+            fn = lambda: om.axpy_sum(0.7, x, y, s, 0, 512, 0, c)
+        else:
+            fn = lambda: om.axpy_sum_queue(kind, 0.7, x, y, s, 0, 512, 0, c)
+        y.copy_(y0)
+        s.zero_()
+        fn()
+        torch.cuda.synchronize()
+        agree &= bool(torch.equal(y, yref))
+        agree &= abs(s.item() - sref.item()) <= 2e-6 * abs(sref.item())
+        us = _time_us(fn, torch)
+        out[f"{kind},c={c}"] = round(12 * n / us / 1e3, 1)
+    return {"n": n, "bytes_per_iter": 12, "gb_s": out, "y_and_sum_agree_with_static": agree}
 
 
 def bench_latency(om, torch):
@@ -540,6 +576,7 @@ def main():
         extra["batched"] = bench_batched(om, torch)
         extra["atomics"] = bench_atomics(om, torch)
         extra["array_reduction"] = bench_array(om, torch)
+        extra["queue_schedules"] = bench_queue(om, torch)
         learned = bench_learned(om, torch)
         if learned is not None:
             extra["learned_picker_heldout"] = learned
