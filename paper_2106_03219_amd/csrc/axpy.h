@@ -79,11 +79,13 @@ __device__ __forceinline__ void axpy_vbatch(float a, const float4* __restrict__ 
 }
 
 // One chunk [lo, hi) of the calling thread.  Where x and y are co-aligned:
-// elements up to 16-byte alignment, vectors up to a 128-byte line boundary,
-// then whole lines -- eight 16-byte vectors of x and of y in flight per lane,
-// so a lane's loads to one line issue together and the line is fetched once
+// up to three elements to 16-byte alignment, vectors up to a 128-byte line
+// boundary and the last up to three elements go first, as one batch; then
+// whole lines -- eight 16-byte vectors of x and of y in flight per lane, so a
+// lane's loads to one line issue together and the line is fetched once
 // (measured at 2^26, chunk 0: 4.26 TB/s with eight, 3.65 with four, 2.91
-// with sixteen) -- then the last vectors and elements.
+// with sixteen); then the last vectors as one batch.  A run's edges thus cost
+// two memory latencies, not four.
 __device__ __forceinline__ void axpy_range(float a, const float* __restrict__ x,
                                            float* __restrict__ y, int64_t lo, int64_t hi,
                                            ff_t& acc) {
@@ -94,16 +96,76 @@ __device__ __forceinline__ void axpy_range(float a, const float* __restrict__ x,
         return;
     }
     const uintptr_t mis = reinterpret_cast<uintptr_t>(y + lo) & 15;
-    const int64_t head = (int64_t)(((16 - mis) & 15) / 4);
-    if (head) axpy_batch<4>(a, x, y, lo, head, acc);
+    const int64_t head = (int64_t)(((16 - mis) & 15) / 4);   // 0..3 elements
     const int64_t p = lo + head;
-    const int64_t nv = (hi - p) / 4;
+    const int64_t nv = (hi - p) / 4;                          // >= 1 (hi - lo >= 8)
+    const int64_t t0 = p + nv * 4;
+    const int64_t tail = hi - t0;                             // 0..3 elements
     const float4* __restrict__ xv = reinterpret_cast<const float4*>(x + p);
     float4* __restrict__ yv = reinterpret_cast<float4*>(y + p);
     constexpr int U = 8;
-    int64_t j = (int64_t)(((128 - (reinterpret_cast<uintptr_t>(yv) & 127)) & 127) / 16);
-    if (j > nv) j = nv;
-    if (j) axpy_vbatch(a, xv, yv, 0, j, acc);
+    int64_t jh = (int64_t)(((128 - (reinterpret_cast<uintptr_t>(yv) & 127)) & 127) / 16);
+    if (jh > nv) jh = nv;                                     // 0..7 head vectors
+
+    if (head | jh | tail) {   // the edges, one batch; an empty group reads
+                              // element lo / vector 0 (inside the run) and
+                              // stores nothing
+        float ex[8], ey[8];
+        int64_t ei[8];
+        float4 vx[U], vy[U];
+        int64_t vj[U];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ei[u] = head ? lo + (u < head ? u : head - 1) : lo;
+            ei[4 + u] = tail ? t0 + (u < tail ? u : tail - 1) : lo;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) vj[u] = jh ? (u < jh ? u : jh - 1) : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            ex[u] = x[ei[u]];
+            ey[u] = y[ei[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vx[u] = xv[vj[u]];
+            vy[u] = yv[vj[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ey[u] = __builtin_fmaf(a, ex[u], ey[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vy[u].x = __builtin_fmaf(a, vx[u].x, vy[u].x);
+            vy[u].y = __builtin_fmaf(a, vx[u].y, vy[u].y);
+            vy[u].z = __builtin_fmaf(a, vx[u].z, vy[u].z);
+            vy[u].w = __builtin_fmaf(a, vx[u].w, vy[u].w);
+        }
+        if (head) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) y[ei[u]] = ey[u];
+        }
+        if (tail) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) y[ei[4 + u]] = ey[4 + u];
+        }
+        if (jh) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) yv[vj[u]] = vy[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) comp_add(acc, u < head ? ey[u] : 0.0f);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool real = u < jh;
+            comp_add(acc, real ? vy[u].x : 0.0f);
+            comp_add(acc, real ? vy[u].y : 0.0f);
+            comp_add(acc, real ? vy[u].z : 0.0f);
+            comp_add(acc, real ? vy[u].w : 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) comp_add(acc, u < tail ? ey[4 + u] : 0.0f);
+    }
+    int64_t j = jh;
     for (; j + U <= nv; j += U) {
         float4 xx[U], yy[U];
 #pragma unroll
@@ -128,8 +190,6 @@ __device__ __forceinline__ void axpy_range(float a, const float* __restrict__ x,
         }
     }
     if (j < nv) axpy_vbatch(a, xv, yv, j, nv - j, acc);
-    const int64_t t0 = p + nv * 4;
-    if (t0 < hi) axpy_batch<4>(a, x, y, t0, hi - t0, acc);
 }
 
 // Chunk size 1: thread t of the block [lo, hi) executes lo + t, lo + t + P,

@@ -128,7 +128,11 @@ __global__ __launch_bounds__(1024) void queue_map_kernel(QueueCfg qc, int64_t n,
 
 // ---------------------------------------------------------------- AXPY + sum
 
-__global__ __launch_bounds__(1024) void queue_axpy_kernel(QueueCfg qc, float a,
+// ONE: dynamic chunks of one iteration (a separate instantiation, so that
+// the register-hungry run code of the other schedules does not cut its
+// occupancy: this path is bound by memory latency).
+template <bool ONE>
+__global__ __launch_bounds__(512) void queue_axpy_kernel(QueueCfg qc, float a,
                                                           const float* __restrict__ x,
                                                           float* __restrict__ y,
                                                           float* __restrict__ sum, int64_t n,
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(1024) void queue_axpy_kernel(QueueCfg qc, float a,
             const float* xb = x + blk.lo;
             float* yb = y + blk.lo;
             while (queue_next(&queue, bq.nchunks, qc.tickets, g)) {
-                if (qc.kind == KIND_DYNAMIC && qc.cmin == 1) {
+                if (ONE) {
                     // one-iteration chunks: the lanes of a wave hold neighbouring
                     // iterations; the tickets' loads issue together
                     constexpr int K = 4;
@@ -358,6 +362,8 @@ extern "C" omprt_status omprt_axpy_sum_queue(float a, const float* d_x, float* d
     if (teams > 65535)
         return fail(OMPRT_ERR_INVALID, "num_teams %d above 65535 (cross-team slot limit)", teams);
     const int threads = s->threads_per_team ? s->threads_per_team : 512;
+    if (threads > 512)
+        return fail(OMPRT_ERR_INVALID, "threads_per_team %d above 512 for this body", threads);
     if (s->n == 0) return OMPRT_OK;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     Workspace* ws = nullptr;
@@ -372,8 +378,12 @@ extern "C" omprt_status omprt_axpy_sum_queue(float a, const float* d_x, float* d
                                    tickets, &qc))
         return st;
     const int block = (threads + kWave - 1) / kWave * kWave;
-    hipLaunchKernelGGL(queue_axpy_kernel, dim3(teams), dim3(block), 0, stream, qc, a, d_x, d_y,
-                       d_sum, s->n, s->dist_chunk, ct);
+    if (kind == KIND_DYNAMIC && qc.cmin == 1)
+        hipLaunchKernelGGL(queue_axpy_kernel<true>, dim3(teams), dim3(block), 0, stream, qc, a,
+                           d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
+    else
+        hipLaunchKernelGGL(queue_axpy_kernel<false>, dim3(teams), dim3(block), 0, stream, qc, a,
+                           d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "queue axpy launch: %s", hipGetErrorString(e));
     return OMPRT_OK;
