@@ -468,6 +468,9 @@ def main():
                          "the reference for scaling HBM byte counters")
     ap.add_argument("--only-axpy", type=int, nargs=2, metavar=("TEAMS", "CHUNK"), default=None,
                     help="only run 3 AXPY+sum launches over 2^26 with 256 threads (profiling)")
+    ap.add_argument("--only-queue", nargs=2, metavar=("KIND", "CHUNK"), default=None,
+                    help="only run 3 AXPY+sum launches over 2^26 under schedule(KIND, CHUNK), "
+                         "KIND dynamic or guided, default teams x 512 threads (profiling)")
     ap.add_argument("--only-array", action="store_true",
                     help="only run the array-section reduction measurements (profiling)")
     args = ap.parse_args()
@@ -494,6 +497,17 @@ def main():
             om.axpy_sum(0.7, x, y, s, teams, 256, 0, chunk)
         torch.cuda.synchronize()
         _log(f"3 AXPY+sum launches over 2^26, {teams} teams x 256 threads, chunk {chunk}")
+        return
+
+    if args.only_queue:
+        kind, chunk = args.only_queue[0], int(args.only_queue[1])
+        x = synth.device(synth.F32, 1 << 26, synth.SEED_AXPY_X)
+        y = synth.device(synth.F32, 1 << 26, synth.SEED_AXPY_Y)
+        s = torch.zeros(1, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            om.axpy_sum_queue(kind, 0.7, x, y, s, 0, 512, 0, chunk)
+        torch.cuda.synchronize()
+        _log(f"3 AXPY+sum launches over 2^26, schedule({kind}, {chunk}), 512 threads")
         return
 
     if args.only_array:
