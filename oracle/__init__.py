@@ -12,8 +12,9 @@ statement of each):
   static ``distribute`` / ``for`` schedules (paper sec. 1: the device runtime
   supplies the routines behind compiler-lowered worksharing loops; sec. 3.1:
   one team is one GPU thread block).
-* :func:`reduce_int`, :func:`reduce_fp` -- ``reduction(op:x)`` results:
-  integer wrap arithmetic, FP64 Neumaier sums, fmax/fmin folds.
+* :func:`reduce_int`, :func:`reduce_fp` -- ``reduction(op:x)`` results for
+  the identifiers + * max min & | ^ && ||: integer wrap arithmetic, FP64
+  Neumaier sums and FP64 products, fmax/fmin folds, 0/1 logical folds.
 * :func:`queue_chunks`, :func:`team_queue` -- dynamic / guided worksharing:
   the chunks each distribute block's queue hands out (owners undefined).
 * :func:`axpy_sum` -- the AXPY worksharing body with fused fmaf.
@@ -34,8 +35,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-SUM, MAX, MIN = 0, 1, 2
-_OPS = {"sum": SUM, "max": MAX, "min": MIN}
+SUM, MAX, MIN, PROD, BAND, BOR, BXOR, LAND, LOR = range(9)
+_OPS = {"sum": SUM, "max": MAX, "min": MIN, "prod": PROD, "band": BAND, "bor": BOR,
+        "bxor": BXOR, "land": LAND, "lor": LOR}
 _FP_DT = {np.dtype(np.float32): 0, np.dtype(np.float64): 1}
 
 _lib = None

@@ -22,10 +22,12 @@
  *    distribute chunks, then threads, then their chunks, then iterations.
  *
  *  - Reductions.  A reduction(op:x) region leaves x = x_orig (op) fold(op,
- *    in[0..n)).  Integers wrap modulo 2^w (computed in the unsigned type of
- *    the same width); signed max/min compare signed.  Floating-point sums
- *    are formed in FP64 with Neumaier's compensated summation of the exactly
- *    widened inputs; floating max/min use fmax/fmin (NaN-dropping).
+ *    in[0..n)), for the OpenMP reduction identifiers + * max min & | ^ && ||.
+ *    Integers wrap modulo 2^w (computed in the unsigned type of the same
+ *    width); signed max/min compare signed.  Floating-point sums are formed
+ *    in FP64 with Neumaier's compensated summation of the exactly widened
+ *    inputs, products in FP64; floating max/min use fmax/fmin
+ *    (NaN-dropping); && and || give 0 or 1.
  *
  *  - AXPY worksharing body: y[i] <- fmaf(a, x[i], y[i]) (one rounding), then
  *    the sum over the updated y in FP64 Neumaier.
@@ -263,39 +265,46 @@ int64_t oracle_team_queue(int kind, int64_t n, int64_t T, int64_t P, int64_t dc,
 /* Reductions                                                               */
 /* ------------------------------------------------------------------------ */
 
-enum { OR_SUM = 0, OR_MAX = 1, OR_MIN = 2 };
+/*
+ * The reduction identifiers of the OpenMP reduction clause: + * max min on
+ * every type, the bitwise & | ^ on integers, the logical && || on every
+ * type (an operand counts as true when it is not zero; the result is 0 or
+ * 1 in x's type).  x_orig takes part as the first operand.
+ */
+enum { OR_SUM = 0, OR_MAX = 1, OR_MIN = 2, OR_PROD = 3, OR_BAND = 4, OR_BOR = 5,
+       OR_BXOR = 6, OR_LAND = 7, OR_LOR = 8 };
 
-/* int32: sum wraps modulo 2^32, max/min compare signed. */
+/* Integer fold in the unsigned type of the same width (sum and product
+ * wrap); max/min compare signed. */
+#define INT_FOLD(S, U)                                                        \
+    {                                                                         \
+        U acc = (U)x;                                                         \
+        S m = x;                                                              \
+        int flag = x != 0;                                                    \
+        for (int64_t i = 0; i < n; i++) {                                     \
+            U v = (U)in[i];                                                   \
+            switch (op) {                                                     \
+            case OR_SUM:  acc += v; break;                                    \
+            case OR_PROD: acc *= v; break;                                    \
+            case OR_BAND: acc &= v; break;                                    \
+            case OR_BOR:  acc |= v; break;                                    \
+            case OR_BXOR: acc ^= v; break;                                    \
+            case OR_MAX:  if (in[i] > m) m = in[i]; break;                    \
+            case OR_MIN:  if (in[i] < m) m = in[i]; break;                    \
+            case OR_LAND: flag = flag && in[i] != 0; break;                   \
+            case OR_LOR:  flag = flag || in[i] != 0; break;                   \
+            }                                                                 \
+        }                                                                     \
+        if (op == OR_MAX || op == OR_MIN) return m;                           \
+        if (op == OR_LAND || op == OR_LOR) return (S)flag;                    \
+        return (S)acc;                                                        \
+    }
+
 int32_t oracle_reduce_i32(const int32_t *in, int64_t n, int op, int32_t x)
-{
-    if (op == OR_SUM) {
-        uint32_t acc = (uint32_t)x;
-        for (int64_t i = 0; i < n; i++) acc += (uint32_t)in[i];
-        return (int32_t)acc;
-    }
-    int32_t acc = x;
-    for (int64_t i = 0; i < n; i++) {
-        if (op == OR_MAX && in[i] > acc) acc = in[i];
-        if (op == OR_MIN && in[i] < acc) acc = in[i];
-    }
-    return acc;
-}
+INT_FOLD(int32_t, uint32_t)
 
-/* int64: sum wraps modulo 2^64, max/min compare signed. */
 int64_t oracle_reduce_i64(const int64_t *in, int64_t n, int op, int64_t x)
-{
-    if (op == OR_SUM) {
-        uint64_t acc = (uint64_t)x;
-        for (int64_t i = 0; i < n; i++) acc += (uint64_t)in[i];
-        return (int64_t)acc;
-    }
-    int64_t acc = x;
-    for (int64_t i = 0; i < n; i++) {
-        if (op == OR_MAX && in[i] > acc) acc = in[i];
-        if (op == OR_MIN && in[i] < acc) acc = in[i];
-    }
-    return acc;
-}
+INT_FOLD(int64_t, uint64_t)
 
 /* Neumaier's compensated summation state (FP64). */
 typedef struct { double s, c; } neum;
@@ -322,7 +331,11 @@ static double bf16_to_double(uint16_t h)
 /*
  * Floating reductions.  dtype: 0 = fp32, 1 = fp64, 2 = bf16 (raw uint16).
  * sum: Neumaier FP64 over x_orig then in[0..n) in index order.
+ * prod: FP64 product in index order, starting at x_orig (each step rounds
+ *   once to FP64, so the result is within (n+1) 2^-53 relative of the exact
+ *   product of the widened inputs, barring overflow and underflow).
  * max/min: fmax/fmin fold starting at x_orig.
+ * land/lor: 0 or 1 (an operand is true when it is not zero; NaN is true).
  * Also returns sum |in[i]| (FP64 Neumaier) through abs_sum when non-NULL,
  * for the condition number kappa = sum|x_i| / |sum x_i|.
  */
@@ -330,7 +343,8 @@ double oracle_reduce_fp(const void *in, int64_t n, int dtype, int op,
                         double x, double *abs_sum)
 {
     neum acc = { x, 0.0 }, aacc = { 0.0, 0.0 };
-    double m = x;
+    double m = x, p = x;
+    int flag = x != 0.0;
     for (int64_t i = 0; i < n; i++) {
         double v;
         if (dtype == 0) v = (double)((const float *)in)[i];
@@ -338,11 +352,17 @@ double oracle_reduce_fp(const void *in, int64_t n, int dtype, int op,
         else v = bf16_to_double(((const uint16_t *)in)[i]);
         if (op == OR_SUM) neum_add(&acc, v);
         else if (op == OR_MAX) m = fmax(m, v);
-        else m = fmin(m, v);
+        else if (op == OR_MIN) m = fmin(m, v);
+        else if (op == OR_PROD) p *= v;
+        else if (op == OR_LAND) flag = flag && v != 0.0;
+        else if (op == OR_LOR) flag = flag || v != 0.0;
         if (abs_sum) neum_add(&aacc, fabs(v));
     }
     if (abs_sum) *abs_sum = aacc.s + aacc.c;
-    return op == OR_SUM ? acc.s + acc.c : m;
+    if (op == OR_SUM) return acc.s + acc.c;
+    if (op == OR_PROD) return p;
+    if (op == OR_LAND || op == OR_LOR) return (double)flag;
+    return m;
 }
 
 /* ------------------------------------------------------------------------ */
