@@ -52,7 +52,21 @@ typedef enum {
     OMPRT_I32 = 0, OMPRT_I64 = 1, OMPRT_F32 = 2, OMPRT_F64 = 3, OMPRT_BF16 = 4
 } omprt_dtype;
 
-typedef enum { OMPRT_SUM = 0, OMPRT_MAX = 1, OMPRT_MIN = 2 } omprt_op;
+/*
+ * The reduction identifiers of the OpenMP reduction clause.  SUM, MAX, MIN,
+ * PROD, LAND and LOR apply to every dtype; BAND, BOR and BXOR to integers
+ * only (UNSUPPORTED otherwise).  Integer SUM and PROD wrap modulo 2^w;
+ * LAND / LOR treat an operand as true when it is not zero (a floating NaN
+ * is true) and give 0 or 1 in x's type (bf16: the bits of 1.0 or 0.0).
+ * fp32 / fp64 / bf16 PROD is compensated (each factor's rounding error is
+ * recovered with a fused multiply-add and carried in a second word); bf16
+ * PROD, like bf16 SUM, returns the fp32 accumulator.  The batched entry
+ * points take SUM, MAX and MIN only.
+ */
+typedef enum {
+    OMPRT_SUM = 0, OMPRT_MAX = 1, OMPRT_MIN = 2, OMPRT_PROD = 3, OMPRT_BAND = 4,
+    OMPRT_BOR = 5, OMPRT_BXOR = 6, OMPRT_LAND = 7, OMPRT_LOR = 8
+} omprt_op;
 
 /*
  * A static worksharing schedule:
@@ -148,10 +162,11 @@ omprt_status omprt_static_map(const omprt_sched *s, int32_t *d_owner,
 
 /*
  * reduction(op:x) over d_in[0..n):  *d_x <- *d_x (op) fold(op, d_in[0..n)).
- * dtype gives d_in's element type.  *d_x has the input's type, except for
- * bf16 sums, whose *d_x is float (the fp32 accumulator).  Integer sums wrap
- * modulo 2^w; max/min compare signed (integers) or follow IEEE maxNum /
- * minNum (floating, NaN-dropping).  fp32 and bf16 sums accumulate in
+ * dtype gives d_in's element type; op any omprt_op defined for it.  *d_x
+ * has the input's type, except for bf16 sums and products, whose *d_x is
+ * float (the fp32 accumulator).  Integer sums wrap modulo 2^w; max/min
+ * compare signed (integers) or follow IEEE maxNum / minNum (floating,
+ * NaN-dropping).  fp32 and bf16 sums accumulate in
  * compensated fp32 (TwoSum per element, float-float combination); fp64 sums
  * in compensated fp64 likewise.  n == 0 leaves *d_x unchanged.  The result is deterministic for a
  * fixed (n, configuration).  Teams follow the static distribute schedule

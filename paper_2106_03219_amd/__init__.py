@@ -10,9 +10,9 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (ATOMIC_ADD, ATOMIC_CAS, ATOMIC_EXCHANGE, ATOMIC_INC, ATOMIC_MAX, BF16,
-                   CFG_NO_MODEL, CFG_STATIC_TILES, F32, F64, I32, I64, MAX, MIN, SUM,
-                   Config, MlpDims, OmprtError, Sched, Segment, check)
+from ._lib import (ATOMIC_ADD, ATOMIC_CAS, ATOMIC_EXCHANGE, ATOMIC_INC, ATOMIC_MAX, BAND, BF16,
+                   BOR, BXOR, CFG_NO_MODEL, CFG_STATIC_TILES, F32, F64, I32, I64, LAND, LOR, MAX,
+                   MIN, PROD, SUM, Config, MlpDims, OmprtError, Sched, Segment, check)
 
 __all__ = [
     "load", "version", "for_static_bounds", "sched_count", "static_map", "reduce",
@@ -21,10 +21,13 @@ __all__ = [
     "mlp_param_count", "mlp_forward", "mlp_loss_grad", "mlp_adam", "model_load",
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
     "workspace_status", "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
-    "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "CFG_NO_MODEL", "CFG_STATIC_TILES",
+    "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "PROD", "BAND", "BOR", "BXOR", "LAND",
+    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "queue_chunk",
+    "queue_map", "axpy_sum_queue",
 ]
 
-_OPS = {"sum": SUM, "max": MAX, "min": MIN}
+_OPS = {"sum": SUM, "max": MAX, "min": MIN, "prod": PROD, "band": BAND, "bor": BOR, "bxor": BXOR,
+        "land": LAND, "lor": LOR}
 
 
 def load():

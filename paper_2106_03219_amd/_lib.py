@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libomprt.so")
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_NOMEM, ERR_DEVICE = range(5)
 I32, I64, F32, F64, BF16 = range(5)
-SUM, MAX, MIN = range(3)
+SUM, MAX, MIN, PROD, BAND, BOR, BXOR, LAND, LOR = range(9)
 ATOMIC_ADD, ATOMIC_INC, ATOMIC_MAX, ATOMIC_EXCHANGE, ATOMIC_CAS = range(5)
 CFG_NO_MODEL = 0x1
 CFG_STATIC_TILES = 0x2

@@ -7,12 +7,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ops.h"
 #include "sched.h"
 
 namespace omprt {
 
-enum { DT_I32 = 0, DT_I64 = 1, DT_F32 = 2, DT_F64 = 3, DT_BF16 = 4, DT_COUNT = 5 };
-enum { OP_SUM = 0, OP_MAX = 1, OP_MIN = 2, OP_COUNT = 3 };
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -435,6 +434,129 @@ template <> struct Red<DT_F64, OP_SUM> : CompSum<double, 2> {
     static __device__ __forceinline__ Out finish(Acc a, Out x) {
         return pair_add(a, Acc{x, 0.0}).hi;
     }
+};
+
+// ---------------------------------------------------------------- more identifiers
+
+// Integer product: wraps modulo 2^w (computed unsigned).
+template <class I, class U>
+struct IntProd {
+    using Acc = U;
+    using Out = I;
+    static constexpr int kNA = 1;
+    static __device__ __forceinline__ Acc identity() { return (U)1; }
+    static __device__ __forceinline__ void elem(Acc& a, I v) { a *= (U)v; }
+    static __device__ __forceinline__ Acc combine(Acc a, Acc b) { return a * b; }
+    static __device__ __forceinline__ Out finish(Acc a, Out x) { return (I)((U)x * a); }
+};
+template <> struct Red<DT_I32, OP_PROD> : IntProd<int32_t, uint32_t> {};
+template <> struct Red<DT_I64, OP_PROD> : IntProd<int64_t, uint64_t> {};
+
+// Bitwise and / or / xor on integers.
+template <class I, class U, int OP>
+struct IntBits {
+    using Acc = U;
+    using Out = I;
+    static constexpr int kNA = 1;
+    static __device__ __forceinline__ Acc identity() { return OP == OP_BAND ? ~(U)0 : (U)0; }
+    static __device__ __forceinline__ Acc combine(Acc a, Acc b) {
+        return OP == OP_BAND ? (a & b) : OP == OP_BOR ? (a | b) : (a ^ b);
+    }
+    static __device__ __forceinline__ void elem(Acc& a, I v) { a = combine(a, (U)v); }
+    static __device__ __forceinline__ Out finish(Acc a, Out x) { return (I)combine((U)x, a); }
+};
+template <> struct Red<DT_I32, OP_BAND> : IntBits<int32_t, uint32_t, OP_BAND> {};
+template <> struct Red<DT_I32, OP_BOR> : IntBits<int32_t, uint32_t, OP_BOR> {};
+template <> struct Red<DT_I32, OP_BXOR> : IntBits<int32_t, uint32_t, OP_BXOR> {};
+template <> struct Red<DT_I64, OP_BAND> : IntBits<int64_t, uint64_t, OP_BAND> {};
+template <> struct Red<DT_I64, OP_BOR> : IntBits<int64_t, uint64_t, OP_BOR> {};
+template <> struct Red<DT_I64, OP_BXOR> : IntBits<int64_t, uint64_t, OP_BXOR> {};
+
+// Logical and / or: an operand is true when it is not zero (NaN is true);
+// the result is 0 or 1 in x's type (bf16: the bits of 1.0 or of 0.0).
+template <class V, class O, int OP>
+struct Logic {
+    using Acc = uint32_t;
+    using Out = O;
+    static constexpr int kNA = 1;
+    static __device__ __forceinline__ Acc identity() { return OP == OP_LAND ? 1u : 0u; }
+    static __device__ __forceinline__ Acc combine(Acc a, Acc b) {
+        return OP == OP_LAND ? (a & b) : (a | b);
+    }
+    static __device__ __forceinline__ void elem(Acc& a, V v) { a = combine(a, v != V(0) ? 1u : 0u); }
+};
+template <class I, int OP>
+struct IntLogic : Logic<I, I, OP> {
+    static __device__ __forceinline__ I finish(uint32_t a, I x) {
+        return (I)Logic<I, I, OP>::combine(x != 0 ? 1u : 0u, a);
+    }
+};
+template <class F, int OP>
+struct FpLogic : Logic<F, F, OP> {
+    static __device__ __forceinline__ F finish(uint32_t a, F x) {
+        return Logic<F, F, OP>::combine(x != F(0) ? 1u : 0u, a) ? F(1) : F(0);
+    }
+};
+template <int OP>
+struct Bf16Logic : Logic<float, uint16_t, OP> {
+    static __device__ __forceinline__ uint16_t finish(uint32_t a, uint16_t x) {
+        const bool xt = __uint_as_float((uint32_t)x << 16) != 0.0f;
+        return Logic<float, uint16_t, OP>::combine(xt ? 1u : 0u, a) ? (uint16_t)0x3F80 : (uint16_t)0;
+    }
+};
+template <> struct Red<DT_I32, OP_LAND> : IntLogic<int32_t, OP_LAND> {};
+template <> struct Red<DT_I32, OP_LOR> : IntLogic<int32_t, OP_LOR> {};
+template <> struct Red<DT_I64, OP_LAND> : IntLogic<int64_t, OP_LAND> {};
+template <> struct Red<DT_I64, OP_LOR> : IntLogic<int64_t, OP_LOR> {};
+template <> struct Red<DT_F32, OP_LAND> : FpLogic<float, OP_LAND> {};
+template <> struct Red<DT_F32, OP_LOR> : FpLogic<float, OP_LOR> {};
+template <> struct Red<DT_F64, OP_LAND> : FpLogic<double, OP_LAND> {};
+template <> struct Red<DT_F64, OP_LOR> : FpLogic<double, OP_LOR> {};
+template <> struct Red<DT_BF16, OP_LAND> : Bf16Logic<OP_LAND> {};
+template <> struct Red<DT_BF16, OP_LOR> : Bf16Logic<OP_LOR> {};
+
+__device__ __forceinline__ float fused_ma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fused_ma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Compensated floating product: a pair (hi, lo) stands for hi + lo.  Each
+// factor's rounding error comes back exactly from a fused multiply-add and
+// gathers in lo; pairs multiply as float-float numbers.  A product that
+// overflows (or is NaN) is returned as the plain product.
+template <class F>
+struct CompProd {
+    using Acc = Pair<F>;
+    static constexpr int kNA = 2;
+    static __device__ __forceinline__ Acc identity() { return Acc{F(1), F(0)}; }
+    static __device__ __forceinline__ void elem(Acc& a, F v) {
+        const F p = a.hi * v;
+        const F e = fused_ma(a.hi, v, -p);
+        a.lo = fused_ma(a.lo, v, e);
+        a.hi = p;
+    }
+    static __device__ __forceinline__ Acc combine(Acc a, Acc b) {
+        const F p = a.hi * b.hi;
+        if (!__builtin_isfinite(p)) return Acc{p, F(0)};
+        F e = fused_ma(a.hi, b.hi, -p);
+        e = fused_ma(a.hi, b.lo, e);
+        e = fused_ma(a.lo, b.hi, e);
+        return fast_two_sum(p, e);
+    }
+    static __device__ __forceinline__ F value(Acc a, F x) {
+        const Acc r = combine(Acc{x, F(0)}, a);
+        return __builtin_isfinite(r.hi) ? r.hi + r.lo : r.hi;
+    }
+};
+template <> struct Red<DT_F32, OP_PROD> : CompProd<float> {
+    using Out = float;
+    static __device__ __forceinline__ Out finish(Acc a, Out x) { return value(a, x); }
+};
+template <> struct Red<DT_F64, OP_PROD> : CompProd<double> {
+    using Out = double;
+    static __device__ __forceinline__ Out finish(Acc a, Out x) { return value(a, x); }
+};
+template <> struct Red<DT_BF16, OP_PROD> : CompProd<float> {
+    using Out = float;   // like bf16 sums: the fp32 accumulator
+    static __device__ __forceinline__ Out finish(Acc a, Out x) { return value(a, x); }
 };
 
 }  // namespace omprt

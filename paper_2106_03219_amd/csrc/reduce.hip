@@ -86,12 +86,26 @@ static Launcher pick(int vi, int ui) {
     return vi == 0 ? UnrollRow<DT, OP, 8>::row[ui] : UnrollRow<DT, OP, 16>::row[ui];
 }
 
+template <int DT, int OP>
+static Launcher pick_if(int vi, int ui) {
+    if constexpr (op_defined(DT, OP))
+        return pick<DT, OP>(vi, ui);
+    else
+        return nullptr;
+}
+
 template <int DT>
 static Launcher pick_op(int op, int vi, int ui) {
     switch (op) {
-        case OP_SUM: return pick<DT, OP_SUM>(vi, ui);
-        case OP_MAX: return pick<DT, OP_MAX>(vi, ui);
-        case OP_MIN: return pick<DT, OP_MIN>(vi, ui);
+        case OP_SUM: return pick_if<DT, OP_SUM>(vi, ui);
+        case OP_MAX: return pick_if<DT, OP_MAX>(vi, ui);
+        case OP_MIN: return pick_if<DT, OP_MIN>(vi, ui);
+        case OP_PROD: return pick_if<DT, OP_PROD>(vi, ui);
+        case OP_BAND: return pick_if<DT, OP_BAND>(vi, ui);
+        case OP_BOR: return pick_if<DT, OP_BOR>(vi, ui);
+        case OP_BXOR: return pick_if<DT, OP_BXOR>(vi, ui);
+        case OP_LAND: return pick_if<DT, OP_LAND>(vi, ui);
+        case OP_LOR: return pick_if<DT, OP_LOR>(vi, ui);
     }
     return nullptr;
 }

@@ -6,6 +6,7 @@
 
 #include "../../include/omprt.h"
 #include "launch.h"
+#include "ops.h"
 
 namespace omprt {
 

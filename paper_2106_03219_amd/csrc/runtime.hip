@@ -45,7 +45,7 @@ int dtype_bytes(int dtype) {
 }
 
 int out_bytes(int dtype, int op) {
-    if (dtype == OMPRT_BF16 && op == OMPRT_SUM) return 4;   // fp32 accumulator
+    if (dtype == OMPRT_BF16 && (op == OMPRT_SUM || op == OMPRT_PROD)) return 4;   // fp32 accumulator
     return dtype_bytes(dtype);
 }
 
@@ -176,11 +176,12 @@ omprt_status resolve_config(int64_t n, int dtype, int op, int body, int64_t chun
     int src = kSrcExplicit;
     if (!full) {
         bool have = false;
-        if (!(cfg && (cfg->flags & OMPRT_CFG_NO_MODEL))) {
+        // the picker and the tuned cache know the sum / max / min kernels only
+        if (op <= OMPRT_MIN && !(cfg && (cfg->flags & OMPRT_CFG_NO_MODEL))) {
             have = model_pick(n, dtype, op, body, chunk, &base);
             if (have) src = kSrcModel;
         }
-        if (!have) {
+        if (!have && op <= OMPRT_MIN) {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune.find(TuneKey{dtype, op, body, floor_log2(n)});
             if (it != g_tune.end()) {
@@ -343,7 +344,7 @@ static omprt_status check_ptr_align(const void* p, int bytes, const char* what) 
 extern "C" omprt_status omprt_reduce(const void* d_in, int64_t n, int32_t dtype, int32_t op,
                                      void* d_x, const omprt_config* cfg, void* hip_stream) {
     if (dtype < 0 || dtype >= DT_COUNT_ABI) return fail(OMPRT_ERR_UNSUPPORTED, "dtype %d", dtype);
-    if (op < 0 || op > 2) return fail(OMPRT_ERR_UNSUPPORTED, "op %d", op);
+    if (!op_defined(dtype, op)) return fail(OMPRT_ERR_UNSUPPORTED, "op %d on dtype %d", op, dtype);
     if (n < 0 || n > kMaxTrip)
         return fail(OMPRT_ERR_INVALID, "n = %lld outside 0..2^50", (long long)n);
     if (!d_x) return fail(OMPRT_ERR_INVALID, "x is NULL");

@@ -117,7 +117,11 @@ def test_reduce_argument_errors_before_device():
     lib = om.load()
     x = ctypes.c_int64(0)
     assert lib.omprt_reduce(None, 5, 9, 0, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
-    assert lib.omprt_reduce(None, 5, 0, 7, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
+    assert lib.omprt_reduce(None, 5, 0, 9, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
+    for op in (_lib.BAND, _lib.BOR, _lib.BXOR):          # bitwise operators: integers only
+        for dt in (_lib.F32, _lib.F64, _lib.BF16):
+            assert lib.omprt_reduce(None, 5, dt, op, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
+        assert lib.omprt_reduce(None, 0, _lib.I64, op, ctypes.byref(x), None, None) == _lib.OK
     assert lib.omprt_reduce(None, -1, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
     assert lib.omprt_reduce(None, 5, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
     assert lib.omprt_reduce(None, 0, 0, 0, None, None, None) == _lib.ERR_INVALID

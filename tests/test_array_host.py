@@ -138,7 +138,8 @@ def test_argument_errors_before_device():
     x = ctypes.c_float(0)
     A = lib.omprt_reduce_array
     assert A(None, 5, 5, 9, 0, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
-    assert A(None, 5, 5, 0, 3, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
+    assert A(None, 5, 5, 0, 9, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED
+    assert A(None, 5, 5, 2, 4, ctypes.byref(x), None, None) == _lib.ERR_UNSUPPORTED   # fp32 &
     assert A(None, -1, 5, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
     assert A(None, 5, -1, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
     assert A(None, 1 << 30, 1 << 30, 0, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
