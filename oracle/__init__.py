@@ -17,6 +17,8 @@ statement of each):
   Neumaier sums and FP64 products, fmax/fmin folds, 0/1 logical folds.
 * :func:`queue_chunks`, :func:`team_queue` -- dynamic / guided worksharing:
   the chunks each distribute block's queue hands out (owners undefined).
+* :func:`reduce_loc` -- maxloc / minloc (value and position, ties to the
+  smaller position).
 * :func:`axpy_sum` -- the AXPY worksharing body with fused fmaf.
 * :func:`atomic_serial` -- the five device atomics (sec. 3.1) applied in
   index order.
@@ -80,6 +82,9 @@ def _load():
     lib.oracle_adam.restype = None
     lib.oracle_atomic_serial.argtypes = [ctypes.c_int, p, i64, p, p, p, p, i64]
     lib.oracle_atomic_serial.restype = i64
+    lib.oracle_reduce_loc.argtypes = [p, i64, ctypes.c_int, ctypes.c_int, i64, ctypes.c_double, i64,
+                                      p, p, p]
+    lib.oracle_reduce_loc.restype = None
     lib.oracle_queue_chunks.argtypes = [ctypes.c_int, i64, i64, i64, p, p, i64]
     lib.oracle_queue_chunks.restype = i64
     lib.oracle_team_queue.argtypes = [ctypes.c_int, i64, i64, i64, i64, i64, i64, p, p, i64]
@@ -251,3 +256,20 @@ def team_queue(kind, n, T, P, dc, c, team):
     hi = np.zeros(max(cnt, 1), dtype=np.int64)
     lib.oracle_team_queue(k, n, T, P, dc, c, team, _ptr(lo), _ptr(hi), cnt)
     return [(int(lo[i]), int(hi[i])) for i in range(cnt)]
+
+
+_LOC_DT = {np.dtype(np.int32): 0, np.dtype(np.int64): 1, np.dtype(np.float32): 2,
+           np.dtype(np.float64): 3}
+
+
+def reduce_loc(a, op, x_val, x_idx, bf16=False):
+    """(value, position) of maxloc (op "max") / minloc ("min") over (x_val, x_idx)
+    and (a[i], i); integers as int, floating values as float."""
+    a = np.ascontiguousarray(a)
+    dt = 4 if bf16 else _LOC_DT[a.dtype]
+    vi, vf, pos = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    integer = dt in (0, 1)
+    _load().oracle_reduce_loc(_ptr(a), a.size, dt, _OPS[op], int(x_val) if integer else 0,
+                              0.0 if integer else float(x_val), int(x_idx), ctypes.byref(vi),
+                              ctypes.byref(vf), ctypes.byref(pos))
+    return (vi.value if integer else vf.value), pos.value

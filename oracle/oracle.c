@@ -29,6 +29,9 @@
  *    inputs, products in FP64; floating max/min use fmax/fmin
  *    (NaN-dropping); && and || give 0 or 1.
  *
+ *  - maxloc / minloc: the largest / smallest value with its position, ties
+ *    to the smaller position (the common user-defined reduction).
+ *
  *  - AXPY worksharing body: y[i] <- fmaf(a, x[i], y[i]) (one rounding), then
  *    the sum over the updated y in FP64 Neumaier.
  *
@@ -363,6 +366,48 @@ double oracle_reduce_fp(const void *in, int64_t n, int dtype, int op,
     if (op == OR_PROD) return p;
     if (op == OR_LAND || op == OR_LOR) return (double)flag;
     return m;
+}
+
+/*
+ * maxloc / minloc, the usual user-defined reduction (a value with its
+ * position): the pairs (x_val, x_idx), (in[0], 0), ..., (in[n-1], n-1) are
+ * folded with "keep the larger (op 1) or smaller (op 2) value; on equal
+ * values keep the smaller position".  That order is total, so the result
+ * does not depend on the fold order.  Floating NaNs never win (as with
+ * fmax/fmin), a NaN x_val loses to any element; -0 and +0 are equal.
+ * dtype: 0 int32, 1 int64, 2 fp32, 3 fp64, 4 bf16 (raw uint16).  Values are
+ * compared as int64 (integers) or as FP64 (floating, exactly widened).  The
+ * winning value is returned through *v_int (integers) or *v_fp (floating)
+ * and its position through *pos.
+ */
+static double loc_value_fp(const void *in, int dtype, int64_t i)
+{
+    if (dtype == 2) return (double)((const float *)in)[i];
+    if (dtype == 3) return ((const double *)in)[i];
+    return bf16_to_double(((const uint16_t *)in)[i]);
+}
+
+void oracle_reduce_loc(const void *in, int64_t n, int dtype, int op,
+                       int64_t x_int, double x_fp, int64_t x_idx,
+                       int64_t *v_int, double *v_fp, int64_t *pos)
+{
+    int64_t bi = x_int, bpos = x_idx;
+    double bf = x_fp;
+    for (int64_t i = 0; i < n; i++) {
+        if (dtype == 0 || dtype == 1) {
+            int64_t v = dtype == 0 ? (int64_t)((const int32_t *)in)[i] : ((const int64_t *)in)[i];
+            int better = op == OR_MAX ? v > bi : v < bi;
+            if (better || (v == bi && i < bpos)) { bi = v; bpos = i; }
+        } else {
+            double v = loc_value_fp(in, dtype, i);
+            if (isnan(v)) continue;
+            int better = isnan(bf) || (op == OR_MAX ? v > bf : v < bf);
+            if (better || (v == bf && i < bpos)) { bf = v; bpos = i; }
+        }
+    }
+    *v_int = bi;
+    *v_fp = bf;
+    *pos = bpos;
 }
 
 /* ------------------------------------------------------------------------ */
