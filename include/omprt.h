@@ -181,6 +181,22 @@ omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
                           void *hip_stream);
 
 /*
+ * maxloc / minloc, the usual user-defined reduction: the largest (op
+ * OMPRT_MAX) or smallest (OMPRT_MIN) value of d_in[0..n) together with its
+ * position.  The pairs (*d_val, *d_idx), (d_in[0], 0), ..., (d_in[n-1],
+ * n-1) are ordered by value, then by the smaller position (so a value that
+ * occurs several times reports its first position, and *d_val / *d_idx take
+ * part like x_orig); floating NaNs never win, -0 and +0 are equal.  On exit
+ * *d_val (the input's type; bf16 bits for bf16) and *d_idx (int64) hold the
+ * first pair of that order.  n == 0 leaves both unchanged.  cfg as for
+ * omprt_reduce, except that loads are 16 bytes (vec_bytes 0 or 16) and the
+ * learned model is not consulted.  UNSUPPORTED for ops other than MAX / MIN.
+ */
+omprt_status omprt_reduce_loc(const void *d_in, int64_t n, int32_t dtype,
+                              int32_t op, void *d_val, int64_t *d_idx,
+                              const omprt_config *cfg, void *hip_stream);
+
+/*
  * Array-section reduction, reduction(op: x[0:m]) over a loop of `rows`
  * iterations whose iteration i contributes d_in[i*m + j] to list item x[j]
  * (d_in row-major, rows x m):
