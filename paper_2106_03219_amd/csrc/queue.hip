@@ -226,6 +226,7 @@ struct DevTable {
 };
 static std::mutex g_qmu;
 static std::map<TableKey, DevTable> g_tables;
+constexpr size_t kMaxTables = 1024;
 
 static omprt_status guided_table(hipStream_t stream, int64_t m, int64_t P, int64_t cmin,
                                  DevTable* out) {
@@ -244,6 +245,16 @@ static omprt_status guided_table(hipStream_t stream, int64_t m, int64_t P, int64
         return fail(OMPRT_ERR_INVALID,
                     "stream is being captured and the guided table for this block size is not "
                     "built yet: make the same call once before capturing");
+    if (g_tables.size() >= kMaxTables) {
+        // many distinct block sizes: drop them all once the device is idle
+        OMPRT_HIP(hipDeviceSynchronize());
+        for (auto& kv : g_tables) {
+            (void)hipSetDevice(kv.first.dev);
+            (void)hipFree(kv.second.ptr);
+        }
+        g_tables.clear();
+        OMPRT_HIP(hipSetDevice(dev));
+    }
     const std::vector<int64_t> b = guided_bounds(m, P, cmin);
     DevTable t;
     t.nchunks = (int64_t)b.size() - 1;
