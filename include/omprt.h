@@ -309,8 +309,9 @@ omprt_status omprt_queue_chunk(int32_t kind, int64_t m, int32_t threads,
  * (the caller zeroes d_count).  tickets: chunks a thread takes per request
  * (1..64).  num_teams and threads_per_team must be given.  Guided chunk
  * bounds are computed on the host once per (block size, threads, chunk)
- * and kept on the device until omprt_finalize (the first call for a block
- * size must not be made while the stream is being captured).
+ * and kept on the device until omprt_finalize, or until 1024 of them exist,
+ * when they are all dropped once the device is idle (the first call for a
+ * block size must not be made while the stream is being captured).
  * Verification kernel for the queue semantics.
  */
 omprt_status omprt_queue_map(const omprt_sched *s, int32_t kind,
