@@ -10,8 +10,9 @@ the timed region), and the CPU baseline leg: the oracle timed on the host over
 the same step, whose results also check the GPU step.  Unless --no-extras:
 the AXPY worksharing body, launch latency, the 4096-segment batched workload
 (plain launches vs one graph-replayed persistent launch), device atomics,
-array-section reductions, the AXPY body under dynamic / guided schedules, and
-the learned picker against the heuristic on held-out instances.
+array-section reductions, the AXPY body under dynamic / guided schedules,
+several reduction variables in one pass, and the learned picker against the
+heuristic on held-out instances.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -132,6 +133,40 @@ def bench_axpy(om, torch):
             "runtime_choice_gb_s": round(12 * n / us / 1e3, 1),
             "y_identical_across_schedules": bool(same_y),
             "sum_spread_across_schedules": spread}
+
+
+def bench_multi(om, torch):
+    """Several reduction variables over one input: reduction(+: s) reduction(max: hi)
+    reduction(min: lo) over 2^28 fp32 and int64 in one fused pass against three plain
+    launches; the fused results must equal the plain ones (max, min, int64 sum exactly,
+    the fp32 sum within 2e-6)."""
+    _log("several reduction variables in one pass")
+    out = {}
+    n = 1 << 28
+    for name, dt in (("fp32", torch.float32), ("int64", torch.int64)):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(95)
+        t = (torch.randn(n, device="cuda", generator=g) if dt == torch.float32 else
+             torch.randint(-(2**40), 2**40, (n,), device="cuda", dtype=dt, generator=g))
+        ident = {"sum": 0, "max": torch.finfo(dt).min if dt.is_floating_point else -(2**63),
+                 "min": torch.finfo(dt).max if dt.is_floating_point else 2**63 - 1}
+        fused = {op: torch.tensor([v], dtype=dt, device="cuda") for op, v in ident.items()}
+        plain = {op: torch.tensor([v], dtype=dt, device="cuda") for op, v in ident.items()}
+        om.reduce_multi(t, list(fused.items()))
+        for op, x in plain.items():
+            om.reduce(t, op, x)
+        torch.cuda.synchronize()
+        ok = all(fused[op].item() == plain[op].item() for op in ("max", "min"))
+        a, b = fused["sum"].item(), plain["sum"].item()
+        ok &= a == b if dt == torch.int64 else abs(a - b) <= 2e-6 * abs(b)
+        us_f = _time_us(lambda: om.reduce_multi(t, list(fused.items())), torch)
+        us_p = _time_us(lambda: [om.reduce(t, op, x) for op, x in plain.items()], torch)
+        out[name] = {"fused_us": round(us_f, 1), "three_launches_us": round(us_p, 1),
+                     "fused_gb_s": round(n * t.element_size() / us_f / 1e3, 1),
+                     "speedup": round(us_p / us_f, 2), "results_agree": bool(ok)}
+        del t
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_queue(om, torch):
@@ -591,6 +626,7 @@ def main():
         extra["atomics"] = bench_atomics(om, torch)
         extra["array_reduction"] = bench_array(om, torch)
         extra["queue_schedules"] = bench_queue(om, torch)
+        extra["several_variables"] = bench_multi(om, torch)
         learned = bench_learned(om, torch)
         if learned is not None:
             extra["learned_picker_heldout"] = learned

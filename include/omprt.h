@@ -181,6 +181,24 @@ omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
                           void *hip_stream);
 
 /*
+ * Several reduction variables of one region over the same input, e.g.
+ *   reduction(+: s) reduction(max: hi) reduction(min: lo)
+ * on one loop over d_in[0..n): nvars (1..3) variables with distinct ops
+ * h_ops[v] among SUM, MAX, MIN and x pointers h_x[v] (host arrays of
+ * device pointers; each x as for omprt_reduce).  One pass over the input
+ * updates every variable; each result equals what omprt_reduce gives for
+ * that op alone (same arithmetic; sums may differ in the last bits from a
+ * separate launch, the accumulation order being the launch's).  cfg as
+ * for omprt_reduce, except 16-byte loads, unroll 2 or 4, no learned model.
+ * UNSUPPORTED for other ops; INVALID for a repeated op, nvars outside 1..3,
+ * NULL or misaligned pointers.
+ */
+omprt_status omprt_reduce_multi(const void *d_in, int64_t n, int32_t dtype,
+                                int32_t nvars, const int32_t *h_ops,
+                                void *const *h_x, const omprt_config *cfg,
+                                void *hip_stream);
+
+/*
  * maxloc / minloc, the usual user-defined reduction: the largest (op
  * OMPRT_MAX) or smallest (OMPRT_MIN) value of d_in[0..n) together with its
  * position.  The pairs (*d_val, *d_idx), (d_in[0], 0), ..., (d_in[n-1],

@@ -22,7 +22,7 @@ __all__ = [
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
     "workspace_status", "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
     "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "PROD", "BAND", "BOR", "BXOR", "LAND",
-    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "queue_chunk",
+    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "queue_chunk",
     "queue_map", "axpy_sum_queue",
 ]
 
@@ -130,6 +130,18 @@ def reduce(inp, op, x, config=None, stream=None, n=None):
     nn = inp.numel() if n is None else int(n)
     check(load().omprt_reduce(_ptr(inp) if nn else (inp.data_ptr() or None), nn, dtype_code(inp),
                               _op(op), _ptr(x), _cfg(config), _stream(stream)), "reduce")
+
+
+def reduce_multi(inp, variables, config=None, stream=None):
+    """Several reduction variables over the same input in one pass:
+    variables = [(op, x tensor), ...] with distinct ops among sum / max / min."""
+    if not inp.is_contiguous():
+        raise ValueError("input must be contiguous")
+    n = inp.numel()
+    ops = (ctypes.c_int32 * len(variables))(*[_op(op) for op, _ in variables])
+    xs = (ctypes.c_void_p * len(variables))(*[_ptr(x) for _, x in variables])
+    check(load().omprt_reduce_multi(_ptr(inp) if n else None, n, dtype_code(inp), len(variables),
+                                    ops, xs, _cfg(config), _stream(stream)), "reduce_multi")
 
 
 def reduce_loc(inp, op, val, idx, config=None, stream=None):

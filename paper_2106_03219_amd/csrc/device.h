@@ -114,6 +114,12 @@ struct CrossTeam {
     uint32_t* status;    // set to 1 if a poll timed out
 };
 constexpr int kSlotWords = 4;                 // 32-bit payload words per slot
+// Slot words a participant's partial of type Acc takes (whole slots: a
+// partial larger than 16 bytes spans several).
+template <class Acc>
+constexpr int slot_words() {
+    return ((int)(sizeof(Acc) / 4) + kSlotWords - 1) / kSlotWords * kSlotWords;
+}
 constexpr uint32_t kPollLimit = 1u << 22;     // polls per slot word before giving up
 
 __device__ __forceinline__ uint32_t read_epoch(const uint32_t* epoch) {
@@ -128,7 +134,7 @@ __device__ __forceinline__ uint32_t launch_tag(uint32_t epoch) { return (epoch <
 
 template <class Acc>
 __device__ __forceinline__ void publish_tagged(const Acc& v, uint64_t* slot, uint32_t tag) {
-    static_assert(sizeof(Acc) % 4 == 0 && sizeof(Acc) / 4 <= kSlotWords, "slot too small");
+    static_assert(sizeof(Acc) % 4 == 0, "partials are whole 32-bit words");
     constexpr int W = sizeof(Acc) / 4;
     uint32_t w[W];
     __builtin_memcpy(w, &v, sizeof(Acc));
@@ -186,15 +192,17 @@ __device__ __forceinline__ bool publish_and_elect(const Acc& partial, uint64_t* 
     return *s_flag != 0;
 }
 
-// Last participant: combine slots [0, count) in index order (thread t takes
-// t, t + P, ...; then the team tree).  Result valid in thread 0.
+// Last participant: combine the partials [0, count) in index order (thread
+// t takes t, t + P, ...; then the team tree).  Partial i starts at word
+// i * slot_words<Acc>().  Result valid in thread 0.
 template <class R>
 __device__ __forceinline__ typename R::Acc combine_slots(const uint64_t* slots, int64_t count,
                                                          uint32_t tag, uint32_t* status,
                                                          typename R::Acc* lds) {
-    typename R::Acc c = R::identity();
+    using Acc = typename R::Acc;
+    Acc c = R::identity();
     for (int64_t i = threadIdx.x; i < count; i += blockDim.x)
-        c = R::combine(c, collect_tagged<typename R::Acc>(slots + i * kSlotWords, tag, status));
+        c = R::combine(c, collect_tagged<Acc>(slots + i * slot_words<Acc>(), tag, status));
     __syncthreads();   // lds may still be read by the previous tree
     return team_reduce<R>(c, lds);
 }

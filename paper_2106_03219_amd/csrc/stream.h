@@ -45,23 +45,20 @@ struct VecLoad<DT_BF16, VB> {
     }
 };
 
-template <int DT, int OP, int VB>
-__device__ __forceinline__ void accumulate_vec(typename Red<DT, OP>::Acc* acc,
+template <class R, int DT, int VB>
+__device__ __forceinline__ void accumulate_vec(typename R::Acc* acc,
                                                const typename VecLoad<DT, VB>::T& v) {
-    using R = Red<DT, OP>;
     using L = VecLoad<DT, VB>;
 #pragma unroll
     for (int e = 0; e < L::PER; ++e) R::elem(acc[e % R::kNA], L::get(v, e));
 }
 
-// acc has Red<DT,OP>::kNA entries; every thread of the team calls this with
-// the same [a, b).
-template <int DT, int OP, int VB, int U>
-__device__ __forceinline__ void stream_range(const typename DType<DT>::S* __restrict__ in,
-                                             int64_t a, int64_t b,
-                                             typename Red<DT, OP>::Acc* acc) {
+// Streaming with any accumulation policy R (elem, kNA, Acc); acc has
+// R::kNA entries; every thread of the team calls this with the same [a, b).
+template <class R, int DT, int VB, int U>
+__device__ __forceinline__ void stream_range_with(const typename DType<DT>::S* __restrict__ in,
+                                                  int64_t a, int64_t b, typename R::Acc* acc) {
     using D = DType<DT>;
-    using R = Red<DT, OP>;
     using S = typename D::S;
     using L = VecLoad<DT, VB>;
     using Vec = typename L::T;
@@ -82,14 +79,22 @@ __device__ __forceinline__ void stream_range(const typename DType<DT>::S* __rest
 #pragma unroll
         for (int u = 0; u < U; ++u) r[u] = L::load(vp + v + (int64_t)u * P);
 #pragma unroll
-        for (int u = 0; u < U; ++u) accumulate_vec<DT, OP, VB>(acc, r[u]);
+        for (int u = 0; u < U; ++u) accumulate_vec<R, DT, VB>(acc, r[u]);
     }
     for (; v < nv; v += P) {
         const Vec r = L::load(vp + v);
-        accumulate_vec<DT, OP, VB>(acc, r);
+        accumulate_vec<R, DT, VB>(acc, r);
     }
     const int64_t t0 = p0 + nv * PER;
     if (tid < b - t0) R::elem(acc[0], D::from(in[t0 + tid]));
+}
+
+// The plain reduction's streaming: policy Red<DT, OP>.
+template <int DT, int OP, int VB, int U>
+__device__ __forceinline__ void stream_range(const typename DType<DT>::S* __restrict__ in,
+                                             int64_t a, int64_t b,
+                                             typename Red<DT, OP>::Acc* acc) {
+    stream_range_with<Red<DT, OP>, DT, VB, U>(in, a, b, acc);
 }
 
 }  // namespace omprt
