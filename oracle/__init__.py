@@ -17,6 +17,7 @@ statement of each):
   Neumaier sums and FP64 products, fmax/fmin folds, 0/1 logical folds.
 * :func:`queue_chunks`, :func:`team_queue` -- dynamic / guided worksharing:
   the chunks each distribute block's queue hands out (owners undefined).
+* :func:`histogram` -- reduction(+: hist[0:bins]) with hist[key[i]] += 1.
 * :func:`reduce_loc` -- maxloc / minloc (value and position, ties to the
   smaller position).
 * :func:`axpy_sum` -- the AXPY worksharing body with fused fmaf.
@@ -82,6 +83,8 @@ def _load():
     lib.oracle_adam.restype = None
     lib.oracle_atomic_serial.argtypes = [ctypes.c_int, p, i64, p, p, p, p, i64]
     lib.oracle_atomic_serial.restype = i64
+    lib.oracle_histogram.argtypes = [p, i64, i32, p]
+    lib.oracle_histogram.restype = i64
     lib.oracle_reduce_loc.argtypes = [p, i64, ctypes.c_int, ctypes.c_int, i64, ctypes.c_double, i64,
                                       p, p, p]
     lib.oracle_reduce_loc.restype = None
@@ -273,3 +276,11 @@ def reduce_loc(a, op, x_val, x_idx, bf16=False):
                               0.0 if integer else float(x_val), int(x_idx), ctypes.byref(vi),
                               ctypes.byref(vf), ctypes.byref(pos))
     return (vi.value if integer else vf.value), pos.value
+
+
+def histogram(keys, bins, hist=None):
+    """(hist + counts of each key in [0, bins), number of keys outside it); int32 wrap."""
+    keys = np.ascontiguousarray(keys, dtype=np.int32)
+    h = np.zeros(bins, dtype=np.int32) if hist is None else np.array(hist, dtype=np.int32, copy=True)
+    sk = _load().oracle_histogram(_ptr(keys), keys.size, int(bins), _ptr(h))
+    return h, int(sk)

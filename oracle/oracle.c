@@ -29,6 +29,8 @@
  *    inputs, products in FP64; floating max/min use fmax/fmin
  *    (NaN-dropping); && and || give 0 or 1.
  *
+ *  - Histogram: reduction(+: hist[0:bins]) with hist[key[i]] += 1.
+ *
  *  - maxloc / minloc: the largest / smallest value with its position, ties
  *    to the smaller position (the common user-defined reduction).
  *
@@ -408,6 +410,23 @@ void oracle_reduce_loc(const void *in, int64_t n, int dtype, int op,
     *v_int = bi;
     *v_fp = bf;
     *pos = bpos;
+}
+
+/*
+ * Histogram: reduction(+: hist[0:bins]) over a loop whose iteration i does
+ * hist[key[i]] += 1 -- an array-section reduction whose list item is chosen
+ * by the data.  Counts wrap modulo 2^32 (int32 list items).  Keys outside
+ * [0, bins) are not counted; returns how many there were.
+ */
+int64_t oracle_histogram(const int32_t *keys, int64_t n, int32_t bins, int32_t *hist)
+{
+    int64_t skipped = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t k = keys[i];
+        if (k < 0 || k >= bins) { skipped++; continue; }
+        hist[k] = (int32_t)((uint32_t)hist[k] + 1u);
+    }
+    return skipped;
 }
 
 /* ------------------------------------------------------------------------ */
