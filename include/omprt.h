@@ -181,6 +181,26 @@ omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
                           void *hip_stream);
 
 /*
+ * Histogram: reduction(+: hist[0:bins]) over a loop whose iteration i does
+ * hist[d_keys[i]] += 1 -- an array-section reduction whose list item is
+ * chosen by the data.  d_hist (bins int32, caller-initialised: its values
+ * take part like x_orig) gets the counts added, modulo 2^32.  Keys outside
+ * [0, bins) are not counted and set bit 4 of the stream's workspace status.
+ * Each team keeps a team-shared copy of the histogram, taken with the
+ * runtime's team-shared allocation, counts its balanced block of keys into
+ * it with atomic adds and adds the copy into d_hist.  Up to 16 256 bins
+ * the copy is in LDS; up to 16 times that, the bins are cut into ranges of
+ * that size, each team counting the keys of one range (every key is read
+ * once per range); beyond, each team's copy is a slice of a global pool
+ * the library keeps per stream (atomics at L2).  cfg: num_teams (default
+ * two per compute unit), threads_per_team (default 512), unroll 1, 2 or 4
+ * (default 4).  bins 1..2^28.
+ */
+omprt_status omprt_histogram(const int32_t *d_keys, int64_t n, int32_t bins,
+                             int32_t *d_hist, const omprt_config *cfg,
+                             void *hip_stream);
+
+/*
  * Several reduction variables of one region over the same input, e.g.
  *   reduction(+: s) reduction(max: hi) reduction(min: lo)
  * on one loop over d_in[0..n): nvars (1..3) variables with distinct ops
@@ -476,7 +496,9 @@ omprt_status omprt_workspace_reset(void *hip_stream);
  * valid -- the cross-team step publishes partials as tagged agent-scope
  * atomics and the last team polls for this launch's tag, so this only
  * happens if a participant was lost, e.g. an aborted launch); bit 2 = an
- * omprt_atomic_apply operation had an out-of-range index.  The bits stay set
+ * omprt_atomic_apply operation had an out-of-range index; bit 4 = an
+ * omprt_histogram key was outside [0, bins); bit 8 = a team-shared
+ * allocation found no room (its launch did nothing).  The bits stay set
  * until omprt_workspace_reset (which also re-zeroes the array-reduction
  * counters).
  */

@@ -22,7 +22,7 @@ __all__ = [
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
     "workspace_status", "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
     "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "PROD", "BAND", "BOR", "BXOR", "LAND",
-    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "queue_chunk",
+    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "queue_chunk",
     "queue_map", "axpy_sum_queue",
 ]
 
@@ -130,6 +130,17 @@ def reduce(inp, op, x, config=None, stream=None, n=None):
     nn = inp.numel() if n is None else int(n)
     check(load().omprt_reduce(_ptr(inp) if nn else (inp.data_ptr() or None), nn, dtype_code(inp),
                               _op(op), _ptr(x), _cfg(config), _stream(stream)), "reduce")
+
+
+def histogram(keys, bins, hist, config=None, stream=None):
+    """hist[k] += number of keys equal to k, for k in [0, bins) (int32 keys and hist)."""
+    if not keys.is_contiguous():
+        raise ValueError("keys must be contiguous")
+    if hist.numel() < bins:
+        raise ValueError("hist has fewer than bins entries")
+    n = keys.numel()
+    check(load().omprt_histogram(_ptr(keys) if n else None, n, int(bins), _ptr(hist), _cfg(config),
+                                 _stream(stream)), "histogram")
 
 
 def reduce_multi(inp, variables, config=None, stream=None):

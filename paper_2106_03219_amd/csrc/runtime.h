@@ -66,6 +66,9 @@ int device_cus();
 void batched_finalize();
 uint32_t* batched_status_word(int dev, hipStream_t stream);
 
+// Histograms (histogram.hip): free the pools.
+void histogram_finalize();
+
 // Dynamic / guided worksharing (queue.hip): free the guided tables.
 void queue_finalize();
 

@@ -518,6 +518,7 @@ extern "C" omprt_status omprt_finalize(void) {
     batched_finalize();
     array_finalize();
     queue_finalize();
+    histogram_finalize();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_ws) {
         if (!kv.second.base) continue;

@@ -207,3 +207,31 @@ def test_atomic_apply_argument_errors():
     assert lib.omprt_atomic_apply(0, None, 1, p, p, None, p, 1, None) == _lib.ERR_INVALID
     assert lib.omprt_atomic_apply(0, p, 1, p, p, None, p, -1, None) == _lib.ERR_INVALID
     assert lib.omprt_atomic_apply(0, None, 0, None, None, None, None, 0, None) == _lib.OK
+
+
+def test_histogram_and_multi_argument_errors():
+    lib = om.load()
+    h = ctypes.c_int32(0)
+    H = lib.omprt_histogram
+    assert H(None, -1, 10, ctypes.byref(h), None, None) == _lib.ERR_INVALID
+    assert H(None, 10, 0, ctypes.byref(h), None, None) == _lib.ERR_INVALID
+    assert H(None, 10, (1 << 28) + 1, ctypes.byref(h), None, None) == _lib.ERR_INVALID
+    assert H(None, 10, 10, None, None, None) == _lib.ERR_INVALID
+    assert H(None, 10, 10, ctypes.byref(h), None, None) == _lib.ERR_INVALID      # NULL keys
+    assert H(None, 0, 10, ctypes.byref(h), None, None) == _lib.OK
+    assert H(ctypes.c_void_p(0x1002), 10, 10, ctypes.byref(h), None, None) == _lib.ERR_INVALID
+    c = om.Config(0, 0, 0, 8, 0, 0)
+    assert H(ctypes.c_void_p(0x1000), 10, 10, ctypes.byref(h), ctypes.byref(c), None) == _lib.ERR_INVALID
+    M = lib.omprt_reduce_multi
+    ops = (ctypes.c_int32 * 2)(0, 0)
+    xs = (ctypes.c_void_p * 2)(0x1000, 0x1010)
+    assert M(ctypes.c_void_p(0x2000), 10, 2, 2, ops, xs, None, None) == _lib.ERR_INVALID   # repeated
+    ops3 = (ctypes.c_int32 * 1)(3)
+    assert M(ctypes.c_void_p(0x2000), 10, 2, 1, ops3, xs, None, None) == _lib.ERR_UNSUPPORTED
+    assert M(ctypes.c_void_p(0x2000), 10, 2, 4, ops, xs, None, None) == _lib.ERR_INVALID
+    assert M(ctypes.c_void_p(0x2000), 10, 2, 1, None, xs, None, None) == _lib.ERR_INVALID
+    L = lib.omprt_reduce_loc
+    i = ctypes.c_int64(0)
+    assert L(None, 10, 2, 0, ctypes.byref(h), ctypes.byref(i), None, None) == _lib.ERR_UNSUPPORTED
+    assert L(None, 0, 2, 1, ctypes.byref(h), ctypes.byref(i), None, None) == _lib.OK
+    assert L(None, 0, 2, 1, None, ctypes.byref(i), None, None) == _lib.ERR_INVALID

@@ -1,0 +1,83 @@
+"""GPU parity of the histogram reduction (reduction(+: hist[0:bins]) with
+hist[key[i]] += 1) against the oracle, exact: bin counts from 1 to 2^20
+(team copies in LDS; ranges of bins, 2 to 16 of them, each in LDS; past
+16 x 16 256 bins, copies in the global pool), uniform and
+single-key (fully contended) inputs, an incoming histogram taking part,
+keys out of range (skipped and flagged), several launch configurations and
+repeated launches."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+BINS = [1, 7, 256, 4096, 16256, 16257, 100000, 260096, 260097, 1 << 20]
+SIZES = [1, 1000, (1 << 20) | 5]
+
+
+def run(om, keys, bins, hist0, config=None):
+    k = torch.from_numpy(np.ascontiguousarray(keys, dtype=np.int32)).cuda()
+    h = torch.from_numpy(np.array(hist0, dtype=np.int32)).cuda()
+    om.histogram(k, bins, h, config=config)
+    torch.cuda.synchronize()
+    return h.cpu().numpy()
+
+
+@pytest.mark.parametrize("bins", BINS)
+def test_uniform_keys(gpu_lib, bins):
+    g = np.random.Generator(np.random.PCG64(bins))
+    for n in SIZES:
+        keys = g.integers(0, bins, n).astype(np.int32)
+        h0 = g.integers(-1000, 1000, bins).astype(np.int32)
+        want, sk = oracle.histogram(keys, bins, hist=h0)
+        assert sk == 0
+        assert np.array_equal(run(gpu_lib, keys, bins, h0), want)
+
+
+@pytest.mark.parametrize("cfg", [{"teams": 1}, {"teams": 4096, "threads": 64}, {"unroll": 1},
+                                 {"threads": 1024, "unroll": 2}])
+def test_configs_and_contention(gpu_lib, cfg):
+    g = np.random.Generator(np.random.PCG64(5))
+    for bins in (300, 50000):
+        keys = g.integers(0, bins, 300001).astype(np.int32)
+        want, _ = oracle.histogram(keys, bins)
+        assert np.array_equal(run(gpu_lib, keys, bins, np.zeros(bins), cfg), want)
+        same = np.full(200003, bins - 1, dtype=np.int32)      # every key on one bin
+        want, _ = oracle.histogram(same, bins)
+        assert np.array_equal(run(gpu_lib, same, bins, np.zeros(bins), cfg), want)
+
+
+def test_out_of_range_keys_flagged(gpu_lib):
+    om = gpu_lib
+    g = np.random.Generator(np.random.PCG64(6))
+    keys = g.integers(-5, 105, 100000).astype(np.int32)
+    want, sk = oracle.histogram(keys, 100)
+    assert sk > 0
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        om.workspace_reset()
+        k = torch.from_numpy(keys).cuda()
+        h = torch.zeros(100, dtype=torch.int32, device="cuda")
+        om.histogram(k, 100, h)
+    s.synchronize()
+    assert np.array_equal(h.cpu().numpy(), want)
+    assert om.workspace_status(stream=s) & 4
+    with torch.cuda.stream(s):
+        om.workspace_reset()
+    assert om.workspace_status(stream=s) == 0
+
+
+def test_repeated_launches_accumulate(gpu_lib):
+    om = gpu_lib
+    g = np.random.Generator(np.random.PCG64(7))
+    for bins in (1000, 30000):
+        keys = g.integers(0, bins, 123457).astype(np.int32)
+        k = torch.from_numpy(keys).cuda()
+        h = torch.zeros(bins, dtype=torch.int32, device="cuda")
+        for _ in range(50):
+            om.histogram(k, bins, h)
+        torch.cuda.synchronize()
+        want, _ = oracle.histogram(keys, bins)
+        assert np.array_equal(h.cpu().numpy(), 50 * want)
