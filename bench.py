@@ -11,8 +11,8 @@ the same step, whose results also check the GPU step.  Unless --no-extras:
 the AXPY worksharing body, launch latency, the 4096-segment batched workload
 (plain launches vs one graph-replayed persistent launch), device atomics,
 array-section reductions, the AXPY body under dynamic / guided schedules,
-several reduction variables in one pass, and the learned picker against the
-heuristic on held-out instances.
+several reduction variables in one pass, maxloc and histograms, and the
+learned picker against the heuristic on held-out instances.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -165,6 +165,37 @@ def bench_multi(om, torch):
                      "fused_gb_s": round(n * t.element_size() / us_f / 1e3, 1),
                      "speedup": round(us_p / us_f, 2), "results_agree": bool(ok)}
         del t
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_loc_hist(om, torch):
+    """maxloc over 2^28 fp32 (checked against torch.argmax's first occurrence) and the
+    histogram of 2^28 uniform int32 keys for 256, 16 257 and 100 000 bins (checked
+    against torch.bincount), default launches."""
+    _log("maxloc and histogram")
+    n = 1 << 28
+    g = torch.Generator(device="cuda")
+    g.manual_seed(97)
+    f = torch.randn(n, device="cuda", generator=g)
+    val = torch.tensor([-float("inf")], device="cuda")
+    idx = torch.tensor([-1], dtype=torch.int64, device="cuda")
+    om.reduce_loc(f, "max", val, idx)
+    torch.cuda.synchronize()
+    ok = idx.item() == int(torch.argmax(f).item()) and val.item() == f.max().item()
+    us = _time_us(lambda: om.reduce_loc(f, "max", val, idx), torch)
+    out = {"maxloc_fp32": {"us": round(us, 1), "gb_s": round(4 * n / us / 1e3, 1), "agrees": ok}}
+    del f
+    for bins in (256, 16257, 100000):
+        k = torch.randint(0, bins, (n,), device="cuda", dtype=torch.int32, generator=g)
+        h = torch.zeros(bins, dtype=torch.int32, device="cuda")
+        om.histogram(k, bins, h)
+        torch.cuda.synchronize()
+        agrees = bool(torch.equal(h.long(), torch.bincount(k.long(), minlength=bins)))
+        us = _time_us(lambda: om.histogram(k, bins, h), torch, reps=3)
+        out[f"histogram_{bins}_bins"] = {"us": round(us, 1), "gkeys_s": round(n / us / 1e3, 1),
+                                         "agrees": agrees}
+        del k
         torch.cuda.empty_cache()
     return out
 
@@ -627,6 +658,7 @@ def main():
         extra["array_reduction"] = bench_array(om, torch)
         extra["queue_schedules"] = bench_queue(om, torch)
         extra["several_variables"] = bench_multi(om, torch)
+        extra["maxloc_histogram"] = bench_loc_hist(om, torch)
         learned = bench_learned(om, torch)
         if learned is not None:
             extra["learned_picker_heldout"] = learned
