@@ -69,10 +69,20 @@ def cpu_baseline(f_host, i_host, passes: int):
         ref_i = oracle.reduce_int(i_host, "sum", 0)
     dt = time.perf_counter() - t0
     step_bytes = f_host.nbytes * 2 + i_host.nbytes
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     baseline = {"value": round(passes * step_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
                 "kind": "oracle",
                 "sample": f"{passes} serial passes of the full step (fp32 sum, fp32 max, int64 "
-                          f"sum over 2^28 each; {dt:.1f} s), FP64 Neumaier sums"}
+                          f"sum over 2^28 each; {dt:.1f} s), FP64 Neumaier sums; 1 core of "
+                          f"{os.cpu_count()} ({cpu_model})"}
     return baseline, (ref_s, abs_s, ref_m, ref_i)
 
 
@@ -635,6 +645,16 @@ def main():
                 "kernel": "omprt::reduce_kernel<1, 0, 16, 4> (int64 sum)", "avg_launch_us": round(kern_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": i.numel() * 8}
 
+    # references on the same data: torch's own reductions and a device copy
+    refs = {}
+    us = _time_us(lambda: torch.sum(i), torch)
+    refs["torch_sum_int64_gb_s"] = round(i.numel() * 8 / us / 1e3, 1)
+    us = _time_us(lambda: torch.sum(f), torch)
+    refs["torch_sum_fp32_gb_s"] = round(f.numel() * 4 / us / 1e3, 1)
+    us = _time_us(lambda: torch.amax(f), torch)
+    refs["torch_amax_fp32_gb_s"] = round(f.numel() * 4 / us / 1e3, 1)
+    roofline["int64_sum_vs_torch_sum"] = round(achieved / refs["torch_sum_int64_gb_s"], 3)
+
     cpu, parity = None, None
     if not args.no_cpu_baseline:
         _log("CPU baseline leg: timing the oracle on the same step, checking the GPU step")
@@ -675,6 +695,7 @@ def main():
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "parity": parity,
         "roofline": roofline,
+        "reference_kernels": refs,
         "cpu_baseline": cpu,
     }
     if "batched" in extra:
