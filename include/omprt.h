@@ -227,8 +227,8 @@ omprt_status omprt_reduce_multi(const void *d_in, int64_t n, int32_t dtype,
  * part like x_orig); floating NaNs never win, -0 and +0 are equal.  On exit
  * *d_val (the input's type; bf16 bits for bf16) and *d_idx (int64) hold the
  * first pair of that order.  n == 0 leaves both unchanged.  cfg as for
- * omprt_reduce, except that loads are 16 bytes (vec_bytes 0 or 16) and the
- * learned model is not consulted.  UNSUPPORTED for ops other than MAX / MIN.
+ * omprt_reduce, except that loads are 16 bytes (vec_bytes 0 or 16), the
+ * default unroll is 8 and the learned model is not consulted.  UNSUPPORTED for ops other than MAX / MIN.
  */
 omprt_status omprt_reduce_loc(const void *d_in, int64_t n, int32_t dtype,
                               int32_t op, void *d_val, int64_t *d_idx,
