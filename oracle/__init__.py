@@ -18,6 +18,8 @@ statement of each):
 * :func:`queue_chunks`, :func:`team_queue` -- dynamic / guided worksharing:
   the chunks each distribute block's queue hands out (owners undefined).
 * :func:`histogram` -- reduction(+: hist[0:bins]) with hist[key[i]] += 1.
+* :func:`power_iteration` -- diagonal power iteration (the generic-mode
+  region's workload), FP64.
 * :func:`reduce_loc` -- maxloc / minloc (value and position, ties to the
   smaller position).
 * :func:`axpy_sum` -- the AXPY worksharing body with fused fmaf.
@@ -83,6 +85,8 @@ def _load():
     lib.oracle_adam.restype = None
     lib.oracle_atomic_serial.argtypes = [ctypes.c_int, p, i64, p, p, p, p, i64]
     lib.oracle_atomic_serial.restype = i64
+    lib.oracle_power_iteration.argtypes = [p, p, i64, i32, p]
+    lib.oracle_power_iteration.restype = None
     lib.oracle_histogram.argtypes = [p, i64, i32, p]
     lib.oracle_histogram.restype = i64
     lib.oracle_reduce_loc.argtypes = [p, i64, ctypes.c_int, ctypes.c_int, i64, ctypes.c_double, i64,
@@ -284,3 +288,12 @@ def histogram(keys, bins, hist=None):
     h = np.zeros(bins, dtype=np.int32) if hist is None else np.array(hist, dtype=np.int32, copy=True)
     sk = _load().oracle_histogram(_ptr(keys), keys.size, int(bins), _ptr(h))
     return h, int(sk)
+
+
+def power_iteration(d, v0, iters):
+    """(v after iters steps, lambda) of w = d*v; s = sum w^2; v = w / sqrt(s), in FP64."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    v = np.array(v0, dtype=np.float64, copy=True)
+    lam = ctypes.c_double()
+    _load().oracle_power_iteration(_ptr(d), _ptr(v), d.size, int(iters), ctypes.byref(lam))
+    return v, lam.value

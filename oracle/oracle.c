@@ -31,6 +31,9 @@
  *
  *  - Histogram: reduction(+: hist[0:bins]) with hist[key[i]] += 1.
  *
+ *  - Power iteration on a diagonal matrix (parallel loops with sequential
+ *    code between them, as a generic-mode target region runs them).
+ *
  *  - maxloc / minloc: the largest / smallest value with its position, ties
  *    to the smaller position (the common user-defined reduction).
  *
@@ -427,6 +430,30 @@ int64_t oracle_histogram(const int32_t *keys, int64_t n, int32_t bins, int32_t *
         hist[k] = (int32_t)((uint32_t)hist[k] + 1u);
     }
     return skipped;
+}
+
+/*
+ * Power iteration on a diagonal matrix, the generic-mode region's workload
+ * (sequential code between parallel loops): iters times
+ *     w[i] = d[i] * v[i];  s = sum w[i]^2;  v[i] = w[i] / sqrt(s)
+ * in FP64, v updated in place; *lambda = sqrt(s) of the last iteration
+ * (the norm of D v, the dominant |d| once v has converged).  iters >= 1.
+ */
+void oracle_power_iteration(const double *d, double *v, int64_t n, int32_t iters,
+                            double *lambda)
+{
+    double s = 0.0;
+    for (int32_t k = 0; k < iters; k++) {
+        neum acc = { 0.0, 0.0 };
+        for (int64_t i = 0; i < n; i++) {
+            v[i] = d[i] * v[i];
+            neum_add(&acc, v[i] * v[i]);
+        }
+        s = acc.s + acc.c;
+        double r = 1.0 / sqrt(s);
+        for (int64_t i = 0; i < n; i++) v[i] = v[i] * r;
+    }
+    *lambda = sqrt(s);
 }
 
 /* ------------------------------------------------------------------------ */
