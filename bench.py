@@ -210,6 +210,48 @@ def bench_loc_hist(om, torch):
     return out
 
 
+def bench_generic(om, torch):
+    """The generic-mode region (power iteration on a diagonal matrix, 100 steps, one team
+    of 1024 threads) against the same region written as one launch per parallel loop
+    (torch: multiply, dot, rsqrt, scale; four launches a step).  Per step the loops move
+    20 bytes an element (read d and v, write v; read and write v)."""
+    import synth
+    _log("generic-mode power iteration")
+    out = {}
+    iters = 100
+    for n in (1 << 12, 1 << 16, 1 << 20):
+        dh, vh = synth.power_inputs(n, 11)
+        d = torch.from_numpy(dh).cuda()
+        v0 = torch.from_numpy(vh).cuda()
+        v = v0.clone()
+        lam = torch.zeros(1, device="cuda")
+        om.generic_power(d, v, iters, lam)
+        torch.cuda.synchronize()
+        us = _time_us(lambda: om.generic_power(d, v, iters, lam), torch, reps=3)
+        w = v0.clone()
+        s = torch.zeros((), device="cuda")
+
+        def per_loop():
+            for _ in range(iters):
+                torch.mul(d, w, out=w)
+                torch.dot(w, w, out=s)
+                w.mul_(torch.rsqrt(s))
+
+        w.copy_(v0)
+        per_loop()
+        torch.cuda.synchronize()
+        v.copy_(v0)
+        om.generic_power(d, v, iters, lam)
+        torch.cuda.synchronize()
+        agrees = bool(torch.allclose(v, w, rtol=1e-4, atol=1e-12))
+        us_t = _time_us(per_loop, torch, reps=3)
+        out[f"n_{n}"] = {"us_per_step": round(us / iters, 2),
+                         "gb_s": round(20 * n * iters / us / 1e3, 1),
+                         "launch_per_loop_us_per_step": round(us_t / iters, 2),
+                         "speedup": round(us_t / us, 2), "agrees": agrees}
+    return out
+
+
 def bench_queue(om, torch):
     """The AXPY + sum body over 2^26 fp32 under schedule(dynamic, c) and schedule(guided,
     c) for the threads of each team (distribute static, one team per compute unit, 512
@@ -549,6 +591,8 @@ def main():
                          "KIND dynamic or guided, default teams x 512 threads (profiling)")
     ap.add_argument("--only-array", action="store_true",
                     help="only run the array-section reduction measurements (profiling)")
+    ap.add_argument("--only-generic", action="store_true",
+                    help="only run the generic-mode power iteration measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -588,6 +632,10 @@ def main():
 
     if args.only_array:
         print(json.dumps({"array_reduction": bench_array(om, torch)}), flush=True)
+        return
+
+    if args.only_generic:
+        print(json.dumps({"generic_power": bench_generic(om, torch)}), flush=True)
         return
 
     if args.calibrate_copy:
@@ -679,6 +727,7 @@ def main():
         extra["queue_schedules"] = bench_queue(om, torch)
         extra["several_variables"] = bench_multi(om, torch)
         extra["maxloc_histogram"] = bench_loc_hist(om, torch)
+        extra["generic_power"] = bench_generic(om, torch)
         learned = bench_learned(om, torch)
         if learned is not None:
             extra["learned_picker_heldout"] = learned

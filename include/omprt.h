@@ -201,6 +201,29 @@ omprt_status omprt_histogram(const int32_t *d_keys, int64_t n, int32_t bins,
                              void *hip_stream);
 
 /*
+ * A target region in generic (non-SPMD) mode: sequential code between
+ * parallel loops, run by one team whose main thread (thread 0) executes the
+ * sequential code and hands each loop to the team through team-shared
+ * memory while the other threads wait at the team barrier for work (the
+ * device runtime's parallel-region hand-off, sec. 2.1).  The region is a
+ * power iteration on diag(d_diag):
+ *   repeat iters times:  w = d .* v;  s = sum w^2;  v = w / sqrt(s)
+ *   *d_lambda = sqrt(s)       (the last s: the norm of D v_(iters-1))
+ * d_v (n floats, device) holds the start vector and is overwritten with the
+ * last normalised vector; d_diag (n floats, device) is read only;
+ * *d_lambda (one float, device) is written.  Loops take the static
+ * schedule with chunk 1; s accumulates in compensated fp32.  A zero vector
+ * gives s = 0 and NaN / infinity results, as the arithmetic says.
+ * threads: 64..1024, a multiple of 64; 0 = 1024.  n 1..2^32, iters >= 1;
+ * d_diag and d_v must not overlap, and d_lambda lies in neither.  One
+ * kernel launch on hip_stream; invalid arguments return OMPRT_ERR_INVALID
+ * before anything is launched.
+ */
+omprt_status omprt_generic_power(const float *d_diag, float *d_v, int64_t n,
+                                 int32_t iters, int32_t threads,
+                                 float *d_lambda, void *hip_stream);
+
+/*
  * Several reduction variables of one region over the same input, e.g.
  *   reduction(+: s) reduction(max: hi) reduction(min: lo)
  * on one loop over d_in[0..n): nvars (1..3) variables with distinct ops

@@ -22,7 +22,7 @@ __all__ = [
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
     "workspace_status", "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
     "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "PROD", "BAND", "BOR", "BXOR", "LAND",
-    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "queue_chunk",
+    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "queue_chunk",
     "queue_map", "axpy_sum_queue",
 ]
 
@@ -141,6 +141,20 @@ def histogram(keys, bins, hist, config=None, stream=None):
     n = keys.numel()
     check(load().omprt_histogram(_ptr(keys) if n else None, n, int(bins), _ptr(hist), _cfg(config),
                                  _stream(stream)), "histogram")
+
+
+def generic_power(diag, v, iters, lam, threads=0, stream=None):
+    """Generic-mode power iteration on diag(diag): iters times w = diag * v,
+    v = w / |w|; lam[0] <- |w| of the last step.  v (fp32, contiguous) is
+    updated in place; one kernel launch."""
+    if not diag.is_contiguous() or not v.is_contiguous():
+        raise ValueError("diag and v must be contiguous")
+    if diag.numel() != v.numel():
+        raise ValueError("diag and v differ in length")
+    if dtype_code(diag) != F32 or dtype_code(v) != F32 or dtype_code(lam) != F32:
+        raise ValueError("diag, v and lam must be float32")
+    check(load().omprt_generic_power(_ptr(diag), _ptr(v), v.numel(), int(iters), int(threads),
+                                     _ptr(lam), _stream(stream)), "generic_power")
 
 
 def reduce_multi(inp, variables, config=None, stream=None):

@@ -47,6 +47,16 @@ def f64_normal(n: int, seed: int) -> np.ndarray:
     return rng(seed).standard_normal(n, dtype=np.float64)
 
 
+def power_inputs(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Diagonal and start vector for the power iteration (fp32): d has a
+    random sign and magnitude uniform on [0.75, 1] (after 100 steps a
+    component has shrunk by at most 0.75^100 ~ 3e-13 against the largest,
+    far from fp32 underflow), v0 is standard normal."""
+    g = rng(seed)
+    d = (g.uniform(0.75, 1.0, n) * g.choice([-1.0, 1.0], n)).astype(np.float32)
+    return d, g.standard_normal(n, dtype=np.float32)
+
+
 def _f32_to_bf16_bits_rne(f: np.ndarray) -> np.ndarray:
     """bfloat16 bit patterns of finite fp32 values, round to nearest even."""
     u = f.view(np.uint32).astype(np.uint64)
