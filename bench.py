@@ -211,23 +211,20 @@ def bench_loc_hist(om, torch):
 
 
 def bench_generic(om, torch):
-    """The generic-mode region (power iteration on a diagonal matrix, 100 steps, one team
-    of 1024 threads) against the same region written as one launch per parallel loop
+    """The generic-mode region (power iteration on a diagonal matrix, 100 steps) with one
+    team of 1024 threads, with the default co-resident teams, and for 2^20 elements a sweep
+    of team counts, against the same region written as one launch per parallel loop
     (torch: multiply, dot, rsqrt, scale; four launches a step).  Per step the loops move
-    20 bytes an element (read d and v, write v; read and write v)."""
+    20 bytes an element (read d and v, write v; read and write v).  Each form's v must
+    agree with the per-loop form's to 1e-4."""
     import synth
     _log("generic-mode power iteration")
     out = {}
     iters = 100
-    for n in (1 << 12, 1 << 16, 1 << 20):
+    for n in (1 << 12, 1 << 16, 1 << 20, 1 << 24):
         dh, vh = synth.power_inputs(n, 11)
         d = torch.from_numpy(dh).cuda()
         v0 = torch.from_numpy(vh).cuda()
-        v = v0.clone()
-        lam = torch.zeros(1, device="cuda")
-        om.generic_power(d, v, iters, lam)
-        torch.cuda.synchronize()
-        us = _time_us(lambda: om.generic_power(d, v, iters, lam), torch, reps=3)
         w = v0.clone()
         s = torch.zeros((), device="cuda")
 
@@ -237,18 +234,29 @@ def bench_generic(om, torch):
                 torch.dot(w, w, out=s)
                 w.mul_(torch.rsqrt(s))
 
-        w.copy_(v0)
         per_loop()
         torch.cuda.synchronize()
-        v.copy_(v0)
-        om.generic_power(d, v, iters, lam)
-        torch.cuda.synchronize()
-        agrees = bool(torch.allclose(v, w, rtol=1e-4, atol=1e-12))
+        want = w.clone()
         us_t = _time_us(per_loop, torch, reps=3)
-        out[f"n_{n}"] = {"us_per_step": round(us / iters, 2),
-                         "gb_s": round(20 * n * iters / us / 1e3, 1),
-                         "launch_per_loop_us_per_step": round(us_t / iters, 2),
-                         "speedup": round(us_t / us, 2), "agrees": agrees}
+        row = {"launch_per_loop_us_per_step": round(us_t / iters, 2)}
+        v = v0.clone()
+        lam = torch.zeros(1, device="cuda")
+        shapes = [("one_team", 1, 1024), ("default", 0, 0)]
+        if n == 1 << 20:
+            shapes += [(f"{t}x{p}", t, p) for t in (64, 128, 256, 512) for p in (256, 1024)]
+        for name, teams, threads in shapes:
+            if n == 1 << 24 and teams == 1:
+                continue
+            v.copy_(v0)
+            om.generic_power(d, v, iters, lam, teams, threads)
+            torch.cuda.synchronize()
+            agrees = bool(torch.allclose(v, want, rtol=1e-4, atol=1e-12))
+            us = _time_us(lambda: om.generic_power(d, v, iters, lam, teams, threads), torch, reps=3)
+            row[name] = {"us_per_step": round(us / iters, 2), "gb_s": round(20 * n * iters / us / 1e3, 1),
+                         "speedup_vs_per_loop": round(us_t / us, 2), "agrees": agrees}
+        out[f"n_{n}"] = row
+        del d, v0, w, v, want
+        torch.cuda.empty_cache()
     return out
 
 

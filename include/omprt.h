@@ -202,8 +202,8 @@ omprt_status omprt_histogram(const int32_t *d_keys, int64_t n, int32_t bins,
 
 /*
  * A target region in generic (non-SPMD) mode: sequential code between
- * parallel loops, run by one team whose main thread (thread 0) executes the
- * sequential code and hands each loop to the team through team-shared
+ * parallel loops, run by teams whose main thread (thread 0) executes the
+ * sequential code and hands each loop to its team through team-shared
  * memory while the other threads wait at the team barrier for work (the
  * device runtime's parallel-region hand-off, sec. 2.1).  The region is a
  * power iteration on diag(d_diag):
@@ -211,16 +211,27 @@ omprt_status omprt_histogram(const int32_t *d_keys, int64_t n, int32_t bins,
  *   *d_lambda = sqrt(s)       (the last s: the norm of D v_(iters-1))
  * d_v (n floats, device) holds the start vector and is overwritten with the
  * last normalised vector; d_diag (n floats, device) is read only;
- * *d_lambda (one float, device) is written.  Loops take the static
- * schedule with chunk 1; s accumulates in compensated fp32.  A zero vector
- * gives s = 0 and NaN / infinity results, as the arithmetic says.
+ * *d_lambda (one float, device) is written.  s accumulates in compensated
+ * fp32.  A zero vector gives s = 0 and NaN / infinity results, as the
+ * arithmetic says.
+ * teams: 1 = one team over the whole loop (the mode's own shape); T > 1 =
+ * T co-resident teams (a cooperative launch), team k owning the balanced
+ * block bal(n, T, k) of both loops and every team running the sequential
+ * code on the same s, which reaches all teams by an all-gather of team
+ * partials through the stream's workspace (a partial that never arrives
+ * sets bit 1 of the workspace status, see omprt_workspace_status); 0 = one
+ * team while n <= 8 * threads, then one team per 8 * threads elements, up
+ * to one per compute unit.  At most 512 teams and no more than fit at once
+ * (OMPRT_ERR_INVALID otherwise); OMPRT_ERR_UNSUPPORTED if the device has no
+ * cooperative launch.  For fixed (teams, threads) the results are
+ * deterministic (the sum's rounding follows its combination order).
  * threads: 64..1024, a multiple of 64; 0 = 1024.  n 1..2^32, iters >= 1;
  * d_diag and d_v must not overlap, and d_lambda lies in neither.  One
  * kernel launch on hip_stream; invalid arguments return OMPRT_ERR_INVALID
  * before anything is launched.
  */
 omprt_status omprt_generic_power(const float *d_diag, float *d_v, int64_t n,
-                                 int32_t iters, int32_t threads,
+                                 int32_t iters, int32_t teams, int32_t threads,
                                  float *d_lambda, void *hip_stream);
 
 /*

@@ -143,18 +143,19 @@ def histogram(keys, bins, hist, config=None, stream=None):
                                  _stream(stream)), "histogram")
 
 
-def generic_power(diag, v, iters, lam, threads=0, stream=None):
+def generic_power(diag, v, iters, lam, teams=0, threads=0, stream=None):
     """Generic-mode power iteration on diag(diag): iters times w = diag * v,
     v = w / |w|; lam[0] <- |w| of the last step.  v (fp32, contiguous) is
-    updated in place; one kernel launch."""
+    updated in place; one kernel launch.  teams 1: one team; T > 1: T
+    co-resident teams; 0: chosen from n."""
     if not diag.is_contiguous() or not v.is_contiguous():
         raise ValueError("diag and v must be contiguous")
     if diag.numel() != v.numel():
         raise ValueError("diag and v differ in length")
     if dtype_code(diag) != F32 or dtype_code(v) != F32 or dtype_code(lam) != F32:
         raise ValueError("diag, v and lam must be float32")
-    check(load().omprt_generic_power(_ptr(diag), _ptr(v), v.numel(), int(iters), int(threads),
-                                     _ptr(lam), _stream(stream)), "generic_power")
+    check(load().omprt_generic_power(_ptr(diag), _ptr(v), v.numel(), int(iters), int(teams),
+                                     int(threads), _ptr(lam), _stream(stream)), "generic_power")
 
 
 def reduce_multi(inp, variables, config=None, stream=None):

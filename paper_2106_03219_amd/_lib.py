@@ -54,7 +54,7 @@ SIGNATURES = {
     "omprt_reduce_loc": (_i32, [_p, _i64, _i32, _i32, _p, _p, _C, _p]),
     "omprt_reduce_multi": (_i32, [_p, _i64, _i32, _i32, _p, _p, _C, _p]),
     "omprt_histogram": (_i32, [_p, _i64, _i32, _p, _C, _p]),
-    "omprt_generic_power": (_i32, [_p, _p, _i64, _i32, _i32, _p, _p]),
+    "omprt_generic_power": (_i32, [_p, _p, _i64, _i32, _i32, _i32, _p, _p]),
     "omprt_reduce_array_plan": (_i32, [_i64, _i64, _i32, _i32, _i32, _C, _p]),
     "omprt_reduce_batched": (_i32, [ctypes.POINTER(Segment), _i32, _C, _p]),
     "omprt_reduce_each": (_i32, [ctypes.POINTER(Segment), _i32, _C, _p]),

@@ -240,13 +240,14 @@ def test_histogram_and_multi_argument_errors():
 def test_generic_power_argument_errors():
     G = om.load().omprt_generic_power
     d, v, lam = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000)
-    assert G(d, v, 0, 1, 0, lam, None) == _lib.ERR_INVALID                  # n < 1
-    assert G(d, v, (1 << 32) + 1, 1, 0, lam, None) == _lib.ERR_INVALID      # n too large
-    assert G(d, v, 16, 0, 0, lam, None) == _lib.ERR_INVALID                 # iters < 1
+    assert G(d, v, 0, 1, 1, 0, lam, None) == _lib.ERR_INVALID                  # n < 1
+    assert G(d, v, (1 << 32) + 1, 1, 1, 0, lam, None) == _lib.ERR_INVALID      # n too large
+    assert G(d, v, 16, 0, 1, 0, lam, None) == _lib.ERR_INVALID                 # iters < 1
+    assert G(d, v, 16, 1, -1, 0, lam, None) == _lib.ERR_INVALID                # teams < 0
     for t in (32, 96 + 1, 1088, -64):
-        assert G(d, v, 16, 1, t, lam, None) == _lib.ERR_INVALID             # threads
-    assert G(None, v, 16, 1, 0, lam, None) == _lib.ERR_INVALID
-    assert G(d, v, 16, 1, 0, None, None) == _lib.ERR_INVALID
-    assert G(ctypes.c_void_p(0x10002), v, 16, 1, 0, lam, None) == _lib.ERR_INVALID   # misaligned
-    assert G(d, ctypes.c_void_p(0x10000 + 60), 16, 1, 0, lam, None) == _lib.ERR_INVALID  # overlap
-    assert G(d, v, 16, 1, 0, ctypes.c_void_p(0x20000 + 8), None) == _lib.ERR_INVALID    # lambda in v
+        assert G(d, v, 16, 1, 1, t, lam, None) == _lib.ERR_INVALID             # threads
+    assert G(None, v, 16, 1, 1, 0, lam, None) == _lib.ERR_INVALID
+    assert G(d, v, 16, 1, 1, 0, None, None) == _lib.ERR_INVALID
+    assert G(ctypes.c_void_p(0x10002), v, 16, 1, 1, 0, lam, None) == _lib.ERR_INVALID   # misaligned
+    assert G(d, ctypes.c_void_p(0x10000 + 60), 16, 1, 1, 0, lam, None) == _lib.ERR_INVALID  # overlap
+    assert G(d, v, 16, 1, 1, 0, ctypes.c_void_p(0x20000 + 8), None) == _lib.ERR_INVALID    # lambda in v
