@@ -260,6 +260,40 @@ def bench_generic(om, torch):
     return out
 
 
+def bench_region(om, torch):
+    """The two-loop region over 2^26 fp32 (AXPY loop, then the sum loop over the updated y)
+    with and without the barrier between the loops, next to the fused body that does both
+    in one loop; default teams and threads, chunks 0, 1 and 64.  The loops move 16 bytes an
+    element (the fused body 12).  y must be bit-identical to the fused body's and the sums
+    within 2e-6 of it."""
+    import synth
+    _log("two-loop region over 2^26 with and without nowait")
+    n = 1 << 26
+    x = synth.device(synth.F32, n, synth.SEED_AXPY_X)
+    y0 = synth.device(synth.F32, n, synth.SEED_AXPY_Y)
+    y = y0.clone()
+    s = torch.zeros(1, dtype=torch.float32, device="cuda")
+    out = {}
+    for c in (0, 1, 64):
+        yref = y0.clone()
+        sref = torch.zeros(1, dtype=torch.float32, device="cuda")
+        om.axpy_sum(0.7, x, yref, sref, 0, 0, 0, c)
+        row = {}
+        forms = (("fused", lambda: om.axpy_sum(0.7, x, y, s, 0, 0, 0, c), 12),
+                 ("barrier", lambda: om.region_axpy_sum(0.7, x, y, s, 0, 0, 0, c, c, False), 16),
+                 ("nowait", lambda: om.region_axpy_sum(0.7, x, y, s, 0, 0, 0, c, c, True), 16))
+        for name, fn, bpe in forms:
+            y.copy_(y0)
+            s.zero_()
+            fn()
+            torch.cuda.synchronize()
+            agrees = bool(torch.equal(y, yref)) and abs(s.item() - sref.item()) <= 2e-6 * abs(sref.item())
+            us = _time_us(fn, torch)
+            row[name] = {"us": round(us, 1), "gb_s": round(bpe * n / us / 1e3, 1), "agrees": agrees}
+        out[f"chunk_{c}"] = row
+    return out
+
+
 def bench_queue(om, torch):
     """The AXPY + sum body over 2^26 fp32 under schedule(dynamic, c) and schedule(guided,
     c) for the threads of each team (distribute static, one team per compute unit, 512
@@ -601,6 +635,8 @@ def main():
                     help="only run the array-section reduction measurements (profiling)")
     ap.add_argument("--only-generic", action="store_true",
                     help="only run the generic-mode power iteration measurements")
+    ap.add_argument("--only-region", action="store_true",
+                    help="only run the two-loop region (nowait) measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -644,6 +680,10 @@ def main():
 
     if args.only_generic:
         print(json.dumps({"generic_power": bench_generic(om, torch)}), flush=True)
+        return
+
+    if args.only_region:
+        print(json.dumps({"region_two_loops": bench_region(om, torch)}), flush=True)
         return
 
     if args.calibrate_copy:
@@ -736,6 +776,7 @@ def main():
         extra["several_variables"] = bench_multi(om, torch)
         extra["maxloc_histogram"] = bench_loc_hist(om, torch)
         extra["generic_power"] = bench_generic(om, torch)
+        extra["region_two_loops"] = bench_region(om, torch)
         learned = bench_learned(om, torch)
         if learned is not None:
             extra["learned_picker_heldout"] = learned

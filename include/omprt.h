@@ -345,6 +345,28 @@ omprt_status omprt_axpy_sum(float a, const float *d_x, float *d_y,
                             float *d_sum, const omprt_sched *s,
                             const omprt_config *cfg, void *hip_stream);
 
+/*
+ * A parallel region with two worksharing loops over the same iterations,
+ * the first with or without its implicit barrier (the nowait clause, whose
+ * routines the device runtime provides for worksharing loops, sec. 2.1):
+ *   loop 1, schedule(static, s->chunk) [nowait]:  y[i] <- fmaf(a, x[i], y[i])
+ *   loop 2, schedule(static, chunk2), reduction(+: sum):  sum += y[i]
+ * Both loops use s's distribute schedule (num_teams, dist_chunk), so a
+ * team executes the same iterations in both and teams never wait for each
+ * other.  nowait != 0 drops the team barrier between the loops; it is only
+ * allowed with chunk2 == s->chunk (the same static schedule puts every
+ * iteration on the same thread in both loops, so each thread reads back
+ * only what it wrote), else OMPRT_ERR_INVALID.  Results equal
+ * omprt_axpy_sum's: y bit for bit, *d_sum <- *d_sum + the compensated fp32
+ * sum of the updated y.  s->num_teams / threads_per_team of 0 let the
+ * runtime pick (as for omprt_axpy_sum); chunk2 >= 0 (0 = one block a
+ * thread).  x and y must not overlap.
+ */
+omprt_status omprt_region_axpy_sum(float a, const float *d_x, float *d_y,
+                                   float *d_sum, const omprt_sched *s,
+                                   int64_t chunk2, int32_t nowait,
+                                   const omprt_config *cfg, void *hip_stream);
+
 /* ----------------------------------------------------------------------- */
 /* Dynamic and guided worksharing                                          */
 /* ----------------------------------------------------------------------- */

@@ -22,7 +22,7 @@ __all__ = [
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
     "workspace_status", "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
     "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "PROD", "BAND", "BOR", "BXOR", "LAND",
-    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "queue_chunk",
+    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "region_axpy_sum", "queue_chunk",
     "queue_map", "axpy_sum_queue",
 ]
 
@@ -230,6 +230,18 @@ def axpy_sum(a, x, y, s, teams=0, threads=0, dist_chunk=0, chunk=0, config=None,
     check(load().omprt_axpy_sum(ctypes.c_float(a), _ptr(x) if x.numel() else None,
                                 _ptr(y) if y.numel() else None, _ptr(s), ctypes.byref(sch),
                                 _cfg(config), _stream(stream)), "axpy_sum")
+
+
+def region_axpy_sum(a, x, y, s, teams=0, threads=0, dist_chunk=0, chunk=0, chunk2=None,
+                    nowait=False, config=None, stream=None):
+    """Two loops in one region: y <- fmaf(a, x, y) under schedule(static, chunk) [nowait],
+    then s[0] += sum(y) under schedule(static, chunk2) (default: chunk)."""
+    sch = _sched(x.numel(), teams, threads, dist_chunk, chunk)
+    c2 = chunk if chunk2 is None else chunk2
+    check(load().omprt_region_axpy_sum(ctypes.c_float(a), _ptr(x) if x.numel() else None,
+                                       _ptr(y) if y.numel() else None, _ptr(s), ctypes.byref(sch),
+                                       int(c2), 1 if nowait else 0, _cfg(config), _stream(stream)),
+          "region_axpy_sum")
 
 
 # ---------------------------------------------------------------- dynamic / guided

@@ -59,6 +59,7 @@ SIGNATURES = {
     "omprt_reduce_batched": (_i32, [ctypes.POINTER(Segment), _i32, _C, _p]),
     "omprt_reduce_each": (_i32, [ctypes.POINTER(Segment), _i32, _C, _p]),
     "omprt_axpy_sum": (_i32, [_f32, _p, _p, _p, _S, _C, _p]),
+    "omprt_region_axpy_sum": (_i32, [_f32, _p, _p, _p, _S, _i64, _i32, _C, _p]),
     "omprt_empty_region": (_i32, [_S, _p]),
     "omprt_atomic_apply": (_i32, [_i32, _p, _i64, _p, _p, _p, _p, _i64, _p]),
     "omprt_queue_chunk": (_i32, [_i32, _i64, _i32, _i64, _i64, _p, _p]),

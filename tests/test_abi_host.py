@@ -251,3 +251,19 @@ def test_generic_power_argument_errors():
     assert G(ctypes.c_void_p(0x10002), v, 16, 1, 1, 0, lam, None) == _lib.ERR_INVALID   # misaligned
     assert G(d, ctypes.c_void_p(0x10000 + 60), 16, 1, 1, 0, lam, None) == _lib.ERR_INVALID  # overlap
     assert G(d, v, 16, 1, 1, 0, ctypes.c_void_p(0x20000 + 8), None) == _lib.ERR_INVALID    # lambda in v
+
+
+def test_region_argument_errors():
+    R = om.load().omprt_region_axpy_sum
+    f = ctypes.c_float(0)
+    x, y = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    s = om.Sched(100, 0, 0, 0, 4)
+    assert R(1.0, x, y, ctypes.byref(f), ctypes.byref(s), 8, 1, None, None) == _lib.ERR_INVALID  # nowait, c1 != c2
+    assert R(1.0, x, y, ctypes.byref(f), ctypes.byref(s), -1, 0, None, None) == _lib.ERR_INVALID  # chunk2 < 0
+    assert R(1.0, x, y, None, ctypes.byref(s), 4, 1, None, None) == _lib.ERR_INVALID             # sum NULL
+    assert R(1.0, x, ctypes.c_void_p(0x10000 + 200), ctypes.byref(f), ctypes.byref(s), 4, 0,
+             None, None) == _lib.ERR_INVALID                                                     # overlap
+    assert R(1.0, None, None, ctypes.byref(f), ctypes.byref(s), 4, 0, None, None) == _lib.ERR_INVALID
+    s0 = om.Sched(0, 1, 64, 0, 4)
+    assert R(1.0, None, None, ctypes.byref(f), ctypes.byref(s0), 4, 1, None, None) == _lib.OK    # n == 0
+    assert R(1.0, None, None, ctypes.byref(f), None, 4, 1, None, None) == _lib.ERR_INVALID
