@@ -640,7 +640,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(this build runs and reports single-GPU throughput)", file=sys.stderr)
+              "(the kernels run on one GPU and the figure is that GPU's throughput; the "
+              "multi-GPU exchange is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
