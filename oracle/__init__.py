@@ -23,6 +23,12 @@ statement of each):
 * :func:`reduce_loc` -- maxloc / minloc (value and position, ties to the
   smaller position).
 * :func:`axpy_sum` -- the AXPY worksharing body with fused fmaf.
+* :func:`udr_fold`, :func:`moments` -- a user-defined reduction (declare
+  reduction) by its sequential definition: the private copy starts at the
+  initializer, the loop body folds the elements in order, the combiner
+  folds the result into the original value; and the count, mean and sum of
+  squared deviations of a sample by their definitions (exactly rounded
+  sums), against which a variance reduction is checked.
 * :func:`atomic_serial` -- the five device atomics (sec. 3.1) applied in
   index order.
 * :func:`mlp_loss_grad`, :func:`adam` -- the learned-configuration
@@ -297,3 +303,28 @@ def power_iteration(d, v0, iters):
     lam = ctypes.c_double()
     _load().oracle_power_iteration(_ptr(d), _ptr(v), d.size, int(iters), ctypes.byref(lam))
     return v, lam.value
+
+
+# ---------------------------------------------------------------- declare reduction
+
+def udr_fold(values, x0, init, body, combiner):
+    """x0 combined with the sequential fold of `values` by a user-defined reduction:
+    priv = init(); priv = body(priv, v_i, i) for i = 0, 1, ...; return combiner(x0, priv).
+    (OpenMP: the private copy is initialised by the initializer, updated by the loop body,
+    and combined into the original list item by the combiner.)"""
+    priv = init()
+    for i, v in enumerate(values):
+        priv = body(priv, v, i)
+    return combiner(x0, priv)
+
+
+def moments(x):
+    """(n, mean, M2) of a sample by definition, in FP64 with exactly rounded sums:
+    mean = sum(x) / n and M2 = sum((x - mean)^2)."""
+    import math
+    xs = [float(v) for v in np.asarray(x).ravel()]
+    n = len(xs)
+    if n == 0:
+        return 0.0, 0.0, 0.0
+    mean = math.fsum(xs) / n
+    return float(n), mean, math.fsum((v - mean) ** 2 for v in xs)
