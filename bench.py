@@ -294,6 +294,50 @@ def bench_region(om, torch):
     return out
 
 
+def bench_udr(om, torch):
+    """User-defined reductions (declared at run time, compiled by hiprtc) over 2^28
+    elements, default launch: Welford's count / mean / M2 over fp32 (checked against
+    torch.var_mean, and timed beside it), an exact three-field integer reduction over int32,
+    and a 16-bin histogram type (64 bytes) over int64."""
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    import udr_cases as U
+    import synth
+    _log("user-defined reductions")
+    n = 1 << 28
+    out = {}
+    for name, dtype in (("WELFORD", synth.F32), ("STATS3", synth.I32), ("HIST16", synth.I64)):
+        c = getattr(U, name)
+        t0 = time.time()
+        h = om.udr_declare(c["type_def"], c["initializer"], c["combiner"], c["body"],
+                           c["acc_bytes"], dtype)
+        compile_s = time.time() - t0
+        data = synth.device(dtype, n, 91)
+        x0 = torch.from_numpy(U.pack(name, getattr(U, name.lower() + "_init")())).cuda()
+        x = x0.clone()
+
+        def fn():
+            x.copy_(x0)
+            om.reduce_udr(h, data, x)
+
+        us = _time_us(fn, torch)
+        row = {"us": round(us, 1), "gb_s": round(n * data.element_size() / us / 1e3, 1),
+               "declare_compile_s": round(compile_s, 2)}
+        if name == "WELFORD":
+            fn()
+            torch.cuda.synchronize()
+            cnt, mean, m2 = U.unpack(name, x.cpu().numpy())
+            var_t, mean_t = torch.var_mean(data, correction=0)
+            row["agrees_with_torch_var_mean"] = bool(
+                cnt == n and abs(mean - mean_t.item()) <= 1e-5 * (abs(mean_t.item()) + var_t.item() ** 0.5)
+                and abs(m2 / n - var_t.item()) <= 1e-5 * var_t.item())
+            us_t = _time_us(lambda: torch.var_mean(data, correction=0), torch)
+            row["torch_var_mean_us"] = round(us_t, 1)
+        out[name.lower()] = row
+        del data
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_queue(om, torch):
     """The AXPY + sum body over 2^26 fp32 under schedule(dynamic, c) and schedule(guided,
     c) for the threads of each team (distribute static, one team per compute unit, 512
@@ -637,6 +681,8 @@ def main():
                     help="only run the generic-mode power iteration measurements")
     ap.add_argument("--only-region", action="store_true",
                     help="only run the two-loop region (nowait) measurements")
+    ap.add_argument("--only-udr", action="store_true",
+                    help="only run the user-defined reduction measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -685,6 +731,10 @@ def main():
 
     if args.only_region:
         print(json.dumps({"region_two_loops": bench_region(om, torch)}), flush=True)
+        return
+
+    if args.only_udr:
+        print(json.dumps({"user_defined_reductions": bench_udr(om, torch)}), flush=True)
         return
 
     if args.calibrate_copy:
@@ -778,6 +828,7 @@ def main():
         extra["maxloc_histogram"] = bench_loc_hist(om, torch)
         extra["generic_power"] = bench_generic(om, torch)
         extra["region_two_loops"] = bench_region(om, torch)
+        extra["user_defined_reductions"] = bench_udr(om, torch)
         learned = bench_learned(om, torch)
         if learned is not None:
             extra["learned_picker_heldout"] = learned

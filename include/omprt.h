@@ -235,6 +235,57 @@ omprt_status omprt_generic_power(const float *d_diag, float *d_v, int64_t n,
                                  float *d_lambda, void *hip_stream);
 
 /*
+ * User-defined reduction (OpenMP's declare reduction): the reduction type,
+ * its initializer, its combiner and the loop body that folds one input
+ * element into a private copy are the caller's device code (C++ text), so
+ *   #pragma omp declare reduction(id : omp_type : combiner) initializer(init)
+ *   #pragma omp target teams distribute parallel for reduction(id : x)
+ *   for (i = 0; i < n; i++) body
+ * becomes one omprt_udr_declare (compiles a kernel with hiprtc for gfx950,
+ * once per distinct source) and omprt_reduce_udr calls.  The runtime
+ * specialises its reduction with the application's code, as the paper does
+ * by linking the runtime into the application as bitcode (sec. 2.2).
+ *   type_def:    defines `omp_type` (trivially copyable; acc_bytes bytes, a
+ *                multiple of 4, at most 64), e.g. "struct omp_type { ... };"
+ *   initializer: statements that set `omp_priv` (omp_type&) to the identity
+ *   combiner:    statements that fold `omp_in` (const omp_type&) into
+ *                `omp_out` (omp_type&); applied in an unspecified order, so
+ *                it must be associative and commutative up to what the
+ *                caller accepts
+ *   body:        statements that fold the element `omp_elem` (int32_t,
+ *                int64_t, float (also for bf16) or double) at position
+ *                `omp_i` (int64_t) into `omp_priv`
+ * The code sees the device headers' names (namespace omprt).  A source that
+ * does not compile returns OMPRT_ERR_INVALID with the compiler's output in
+ * omprt_last_error().  *h_handle receives a handle for omprt_reduce_udr;
+ * declaring the same source and dtype again returns the same handle.
+ */
+typedef struct {
+    const char *type_def;
+    const char *initializer;
+    const char *combiner;
+    const char *body;
+    int32_t acc_bytes;
+} omprt_udr_source;
+
+omprt_status omprt_udr_declare(const omprt_udr_source *src, int32_t dtype,
+                               int32_t *h_handle);
+
+/*
+ * x <- combiner(x, r), r the reduction of d_in[0..n) (dtype as declared)
+ * under the declared reduction: teams take balanced blocks, a lane folds
+ * its elements into a private copy with the body in increasing position,
+ * copies combine through the team tree and the last team.  d_x points to
+ * one omp_type in device memory (4-byte aligned); n == 0 leaves it
+ * unchanged.  cfg: num_teams and threads_per_team (others must be 0).  The
+ * first call on a device loads the kernel's module there (gfx950 only).
+ * Deterministic for fixed (n, configuration).
+ */
+omprt_status omprt_reduce_udr(int32_t handle, const void *d_in, int64_t n,
+                              void *d_x, const omprt_config *cfg,
+                              void *hip_stream);
+
+/*
  * Several reduction variables of one region over the same input, e.g.
  *   reduction(+: s) reduction(max: hi) reduction(min: lo)
  * on one loop over d_in[0..n): nvars (1..3) variables with distinct ops

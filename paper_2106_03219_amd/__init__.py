@@ -22,7 +22,7 @@ __all__ = [
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
     "workspace_status", "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
     "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "PROD", "BAND", "BOR", "BXOR", "LAND",
-    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "region_axpy_sum", "queue_chunk",
+    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "region_axpy_sum", "udr_declare", "reduce_udr", "queue_chunk",
     "queue_map", "axpy_sum_queue",
 ]
 
@@ -156,6 +156,27 @@ def generic_power(diag, v, iters, lam, teams=0, threads=0, stream=None):
         raise ValueError("diag, v and lam must be float32")
     check(load().omprt_generic_power(_ptr(diag), _ptr(v), v.numel(), int(iters), int(teams),
                                      int(threads), _ptr(lam), _stream(stream)), "generic_power")
+
+
+def udr_declare(type_def, initializer, combiner, body, acc_bytes, dtype):
+    """declare reduction: compile the user's reduction type (named omp_type), initializer
+    (sets omp_priv), combiner (folds omp_in into omp_out) and loop body (folds omp_elem at
+    position omp_i into omp_priv) for inputs of `dtype` (a dtype code); returns a handle."""
+    src = _lib.UdrSource(type_def.encode(), initializer.encode(), combiner.encode(),
+                         body.encode(), int(acc_bytes))
+    h = ctypes.c_int32(-1)
+    check(load().omprt_udr_declare(ctypes.byref(src), int(dtype), ctypes.byref(h)), "udr_declare")
+    return h.value
+
+
+def reduce_udr(handle, inp, x, config=None, stream=None):
+    """x <- combiner(x, reduction of inp) under a declared reduction; x is a device
+    tensor holding one omp_type (its bytes)."""
+    if not inp.is_contiguous():
+        raise ValueError("input must be contiguous")
+    n = inp.numel()
+    check(load().omprt_reduce_udr(int(handle), _ptr(inp) if n else None, n, _ptr(x), _cfg(config),
+                                  _stream(stream)), "reduce_udr")
 
 
 def reduce_multi(inp, variables, config=None, stream=None):

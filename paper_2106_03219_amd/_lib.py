@@ -36,6 +36,12 @@ class Segment(ctypes.Structure):
                 ("op", ctypes.c_int32), ("d_x", ctypes.c_void_p)]
 
 
+class UdrSource(ctypes.Structure):
+    _fields_ = [("type_def", ctypes.c_char_p), ("initializer", ctypes.c_char_p),
+                ("combiner", ctypes.c_char_p), ("body", ctypes.c_char_p),
+                ("acc_bytes", ctypes.c_int32)]
+
+
 class MlpDims(ctypes.Structure):
     _fields_ = [("F", ctypes.c_int32), ("H1", ctypes.c_int32), ("H2", ctypes.c_int32),
                 ("K", ctypes.c_int32)]
@@ -54,6 +60,8 @@ SIGNATURES = {
     "omprt_reduce_loc": (_i32, [_p, _i64, _i32, _i32, _p, _p, _C, _p]),
     "omprt_reduce_multi": (_i32, [_p, _i64, _i32, _i32, _p, _p, _C, _p]),
     "omprt_histogram": (_i32, [_p, _i64, _i32, _p, _C, _p]),
+    "omprt_udr_declare": (_i32, [ctypes.POINTER(UdrSource), _i32, ctypes.POINTER(_i32)]),
+    "omprt_reduce_udr": (_i32, [_i32, _p, _i64, _p, _C, _p]),
     "omprt_generic_power": (_i32, [_p, _p, _i64, _i32, _i32, _i32, _p, _p]),
     "omprt_reduce_array_plan": (_i32, [_i64, _i64, _i32, _i32, _i32, _C, _p]),
     "omprt_reduce_batched": (_i32, [ctypes.POINTER(Segment), _i32, _C, _p]),

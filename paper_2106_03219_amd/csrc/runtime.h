@@ -69,6 +69,9 @@ uint32_t* batched_status_word(int dev, hipStream_t stream);
 // Histograms (histogram.hip): free the pools.
 void histogram_finalize();
 
+// User-defined reductions (udr.hip): unload the loaded modules.
+void udr_finalize();
+
 // Dynamic / guided worksharing (queue.hip): free the guided tables.
 void queue_finalize();
 

@@ -24,7 +24,7 @@ namespace omprt {
 static thread_local std::string t_err;
 
 omprt_status fail(omprt_status st, const char* fmt, ...) {
-    char buf[512];
+    char buf[2048];   // room for a compiler log excerpt
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
@@ -519,6 +519,7 @@ extern "C" omprt_status omprt_finalize(void) {
     array_finalize();
     queue_finalize();
     histogram_finalize();
+    udr_finalize();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_ws) {
         if (!kv.second.base) continue;

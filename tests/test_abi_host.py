@@ -267,3 +267,38 @@ def test_region_argument_errors():
     s0 = om.Sched(0, 1, 64, 0, 4)
     assert R(1.0, None, None, ctypes.byref(f), ctypes.byref(s0), 4, 1, None, None) == _lib.OK    # n == 0
     assert R(1.0, None, None, ctypes.byref(f), None, 4, 1, None, None) == _lib.ERR_INVALID
+
+
+def test_udr_declare_compiles_and_reports_errors():
+    """declare reduction compiles with hiprtc on the host (no device needed): a valid source
+    gives a handle (the same one when declared again), user errors come back as
+    OMPRT_ERR_INVALID with the compiler's message."""
+    import udr_cases as U
+    c = U.WELFORD
+    h = om.udr_declare(c["type_def"], c["initializer"], c["combiner"], c["body"], c["acc_bytes"], om.F32)
+    assert h >= 0
+    assert om.udr_declare(c["type_def"], c["initializer"], c["combiner"], c["body"], c["acc_bytes"],
+                          om.F32) == h
+    assert om.udr_declare(c["type_def"], c["initializer"], c["combiner"], c["body"], c["acc_bytes"],
+                          om.BF16) != h
+    with pytest.raises(om.OmprtError) as e:         # a missing semicolon in the combiner
+        om.udr_declare("struct omp_type { int a; };", "omp_priv.a = 0;", "omp_out.a += omp_in.a",
+                       "omp_priv.a += omp_elem;", 4, om.I32)
+    assert e.value.status == _lib.ERR_INVALID and "combiner" in str(e.value)
+    with pytest.raises(om.OmprtError) as e:         # declared size differs from sizeof
+        om.udr_declare("struct omp_type { int a; };", "omp_priv.a = 0;", "omp_out.a += omp_in.a;",
+                       "omp_priv.a += omp_elem;", 8, om.I32)
+    assert "acc_bytes" in str(e.value)
+    for bad in (0, 2, 68):
+        with pytest.raises(om.OmprtError):
+            om.udr_declare("struct omp_type { int a; };", "", "", "", bad, om.I32)
+    with pytest.raises(om.OmprtError):
+        om.udr_declare("struct omp_type { int a; };", "", "", "", 4, 9)          # dtype
+    lib = om.load()
+    x = ctypes.c_int32(0)
+    assert lib.omprt_reduce_udr(10 ** 6, None, 0, ctypes.byref(x), None, None) == _lib.ERR_INVALID
+    assert lib.omprt_reduce_udr(h, None, 5, ctypes.byref(x), None, None) == _lib.ERR_INVALID
+    assert lib.omprt_reduce_udr(h, None, 0, None, None, None) == _lib.ERR_INVALID
+    cfg = om.Config(0, 0, 16, 0, 0, 0)
+    assert lib.omprt_reduce_udr(h, None, 0, ctypes.byref(x), ctypes.byref(cfg), None) == _lib.ERR_INVALID
+    assert lib.omprt_reduce_udr(h, None, 0, ctypes.byref(x), None, None) == _lib.OK   # n == 0
