@@ -181,8 +181,8 @@ def bench_multi(om, torch):
 
 def bench_loc_hist(om, torch):
     """maxloc over 2^28 fp32 (checked against torch.argmax's first occurrence) and the
-    histogram of 2^28 uniform int32 keys for 256, 16 257 and 100 000 bins (checked
-    against torch.bincount), default launches."""
+    histogram of 2^28 uniform int32 keys for 256, 16 257, 100 000 and 2^20 bins, default
+    strategy and atomics on hist (checked against torch.bincount), default launches."""
     _log("maxloc and histogram")
     n = 1 << 28
     g = torch.Generator(device="cuda")
@@ -196,16 +196,32 @@ def bench_loc_hist(om, torch):
     us = _time_us(lambda: om.reduce_loc(f, "max", val, idx), torch)
     out = {"maxloc_fp32": {"us": round(us, 1), "gb_s": round(4 * n / us / 1e3, 1), "agrees": ok}}
     del f
-    for bins in (256, 16257, 100000):
+    out.update(bench_hist(om, torch, (256, 16257, 100000, 1 << 20), g))
+    return out
+
+
+def bench_hist(om, torch, bin_counts, g=None):
+    """Histograms of 2^28 uniform int32 keys: the default strategy and atomics on hist
+    (HIST_DIRECT), each checked against torch.bincount."""
+    n = 1 << 28
+    if g is None:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(97)
+    out = {}
+    for bins in bin_counts:
         k = torch.randint(0, bins, (n,), device="cuda", dtype=torch.int32, generator=g)
+        want = torch.bincount(k.long(), minlength=bins)
         h = torch.zeros(bins, dtype=torch.int32, device="cuda")
-        om.histogram(k, bins, h)
-        torch.cuda.synchronize()
-        agrees = bool(torch.equal(h.long(), torch.bincount(k.long(), minlength=bins)))
-        us = _time_us(lambda: om.histogram(k, bins, h), torch, reps=3)
-        out[f"histogram_{bins}_bins"] = {"us": round(us, 1), "gkeys_s": round(n / us / 1e3, 1),
-                                         "agrees": agrees}
-        del k
+        for name, cfg in (("", None), ("_direct", {"flags": om.CFG_HIST_DIRECT})):
+            h.zero_()
+            om.histogram(k, bins, h, config=cfg)
+            torch.cuda.synchronize()
+            agrees = bool(torch.equal(h.long(), want))
+            us = _time_us(lambda: om.histogram(k, bins, h, config=cfg), torch, reps=3)
+            out[f"histogram_{bins}_bins{name}"] = {"us": round(us, 1),
+                                                   "gkeys_s": round(n / us / 1e3, 3),
+                                                   "agrees": agrees}
+        del k, want
         torch.cuda.empty_cache()
     return out
 
@@ -683,6 +699,8 @@ def main():
                     help="only run the two-loop region (nowait) measurements")
     ap.add_argument("--only-udr", action="store_true",
                     help="only run the user-defined reduction measurements")
+    ap.add_argument("--only-hist", action="store_true",
+                    help="only run the histogram strategy sweep over bin counts")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -735,6 +753,11 @@ def main():
 
     if args.only_udr:
         print(json.dumps({"user_defined_reductions": bench_udr(om, torch)}), flush=True)
+        return
+
+    if args.only_hist:
+        bins = (256, 4096, 16256, 16257, 65536, 260096, 520192, 520193, 1 << 20, 1 << 24)
+        print(json.dumps({"histogram": bench_hist(om, torch, bins)}), flush=True)
         return
 
     if args.calibrate_copy:

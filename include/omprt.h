@@ -109,6 +109,11 @@ typedef struct {
 #define OMPRT_CFG_NO_MODEL 0x1u      /* ignore the learned model for this call */
 #define OMPRT_CFG_STATIC_TILES 0x2u  /* batched: deal tiles round-robin instead of
                                         by atomic ticket */
+#define OMPRT_CFG_HIST_TEAM_COPY 0x4u  /* histogram: past the LDS bin ranges, team
+                                          copies in the global pool instead of
+                                          atomics on hist */
+#define OMPRT_CFG_HIST_DIRECT 0x8u     /* histogram: atomics on hist for any bin
+                                          count (no team copy) */
 
 /* One independent reduction of a batch.  x follows omprt_reduce. */
 typedef struct {
@@ -189,12 +194,15 @@ omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
  * Each team keeps a team-shared copy of the histogram, taken with the
  * runtime's team-shared allocation, counts its balanced block of keys into
  * it with atomic adds and adds the copy into d_hist.  Up to 16 256 bins
- * the copy is in LDS; up to 16 times that, the bins are cut into ranges of
+ * the copy is in LDS; up to 32 times that, the bins are cut into ranges of
  * that size, each team counting the keys of one range (every key is read
- * once per range); beyond, each team's copy is a slice of a global pool
- * the library keeps per stream (atomics at L2).  cfg: num_teams (default
- * two per compute unit), threads_per_team (default 512), unroll 1, 2 or 4
- * (default 4).  bins 1..2^28.
+ * once per range); beyond, every key is an atomic add on d_hist itself (no
+ * copy).  cfg->flags OMPRT_CFG_HIST_TEAM_COPY keeps team copies past the
+ * ranges, each a slice of a global pool the library keeps per stream
+ * (team-shared allocation falling back from LDS; atomics at L2);
+ * OMPRT_CFG_HIST_DIRECT takes atomics on d_hist for any bin count.  cfg:
+ * num_teams (default two per compute unit), threads_per_team (default
+ * 512), unroll 1, 2 or 4 (default 4).  bins 1..2^28.
  */
 omprt_status omprt_histogram(const int32_t *d_keys, int64_t n, int32_t bins,
                              int32_t *d_hist, const omprt_config *cfg,

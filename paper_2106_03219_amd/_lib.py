@@ -17,6 +17,8 @@ SUM, MAX, MIN, PROD, BAND, BOR, BXOR, LAND, LOR = range(9)
 ATOMIC_ADD, ATOMIC_INC, ATOMIC_MAX, ATOMIC_EXCHANGE, ATOMIC_CAS = range(5)
 CFG_NO_MODEL = 0x1
 CFG_STATIC_TILES = 0x2
+CFG_HIST_TEAM_COPY = 0x4
+CFG_HIST_DIRECT = 0x8
 
 
 class Sched(ctypes.Structure):

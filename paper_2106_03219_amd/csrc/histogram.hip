@@ -3,7 +3,8 @@
 // chosen by the data.  Each team takes a team-shared copy of (a range of)
 // the histogram with team_alloc (in LDS when it fits, else in its slice of
 // a global pool), counts its balanced block of keys into it with atomic
-// adds, and adds the non-zero bins of its copy into hist.  Counts wrap modulo 2^32; keys
+// adds, and adds the non-zero bins of its copy into hist.  Past the LDS
+// ranges the default is no copy at all: atomic adds on hist.  Counts wrap modulo 2^32; keys
 // outside [0, bins) are not counted and set bit 3 (value 4) of the stream's
 // workspace status.
 #include <algorithm>
@@ -143,6 +144,62 @@ __global__ __launch_bounds__(1024) void histogram_kernel(const int32_t* __restri
     team_free(&st, h, (uint64_t)r.tb * 4);
 }
 
+// Without a team copy: every key is an atomic add on hist itself (performed
+// at the memory side's atomic units, coherent across the XCDs).  For bins
+// far beyond LDS this is the cheaper reduction: no copy to zero and merge,
+// and few keys meet on one bin.
+template <int U>
+__global__ __launch_bounds__(1024) void histogram_direct_kernel(const int32_t* __restrict__ keys,
+                                                                int64_t n, uint32_t bins,
+                                                                int32_t* __restrict__ hist,
+                                                                uint32_t* status) {
+    __shared__ int s_bad;
+    const int tid = threadIdx.x;
+    const int64_t P = blockDim.x;
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    uint32_t* h = reinterpret_cast<uint32_t*>(hist);
+    bool bad = false;
+    auto count = [&](int32_t k) {
+        if ((uint32_t)k >= bins)
+            bad = true;
+        else
+            __hip_atomic_fetch_add(h + k, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    const Range blk = bal_share(n, gridDim.x, blockIdx.x);
+    if (blk.lo < blk.hi) {
+        const int64_t a = blk.lo, e = blk.hi;
+        const uintptr_t mis = reinterpret_cast<uintptr_t>(keys + a) & 15;
+        int64_t head = (int64_t)(((16 - mis) & 15) / 4);
+        if (head > e - a) head = e - a;
+        if (tid < head) count(keys[a + tid]);
+        const int64_t p0 = a + head;
+        const int64_t nv = (e - p0) / 4;
+        using i32x4 = int32_t __attribute__((ext_vector_type(4)));
+        const i32x4* __restrict__ vp = reinterpret_cast<const i32x4*>(keys + p0);
+        int64_t v = tid;
+        for (; v + (U - 1) * P < nv; v += U * P) {
+            i32x4 r[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) r[u] = __builtin_nontemporal_load(vp + v + u * P);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) count(r[u][q]);
+        }
+        for (; v < nv; v += P) {
+            const i32x4 r = __builtin_nontemporal_load(vp + v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) count(r[q]);
+        }
+        const int64_t t0 = p0 + nv * 4;
+        if (tid < e - t0) count(keys[t0 + tid]);
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+    if (tid == 0 && s_bad) __hip_atomic_fetch_or(status, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Global pool of the team copies that do not fit LDS: per (device, stream),
 // grown on demand outside capture.
 struct Pool {
@@ -187,7 +244,10 @@ void histogram_finalize() {
 }
 
 constexpr uint32_t kHistLds = 64 * 1024 - 512;   // dynamic LDS per team
-constexpr uint32_t kMaxBinTiles = 16;             // bin ranges before the global pool
+// Bin ranges before atomics on hist: a key is read once per range, so ranges
+// cost about 1.6 T keys/s / ranges at 2^28 keys (2: 808 G/s, 16: 125 G/s)
+// against about 27 G keys/s for atomics on hist; 32 ranges keep a 2x margin.
+constexpr uint32_t kMaxBinTiles = 32;
 
 }  // namespace omprt
 
@@ -216,16 +276,37 @@ extern "C" omprt_status omprt_histogram(const int32_t* d_keys, int64_t n, int32_
         if (cfg->threads_per_team) threads = cfg->threads_per_team;
         if (cfg->unroll) unroll = cfg->unroll;
     }
+    const uint32_t flags = cfg ? cfg->flags : 0u;
+    if ((flags & OMPRT_CFG_HIST_DIRECT) && (flags & OMPRT_CFG_HIST_TEAM_COPY))
+        return fail(OMPRT_ERR_INVALID, "HIST_DIRECT and HIST_TEAM_COPY exclude each other");
     if (n == 0) return OMPRT_OK;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     // Bins that do not fit one team's LDS are cut into up to kMaxBinTiles
     // ranges, each counted by its own teams (every team reads its block of
     // the keys and counts those in its range: tiles x the key traffic, at
-    // LDS atomic speed); past that the team copies go to the global pool
-    // (atomics at L2).
+    // LDS atomic speed); past that, atomics on hist, or on request team
+    // copies in the global pool (atomics at L2, then a merge).
     constexpr uint32_t lds_bins = kHistLds / 4 / 4 * 4;
     uint32_t tiles = (uint32_t)((bins + lds_bins - 1) / lds_bins);
     uint32_t tile_bins = tiles > 1 ? (uint32_t)((bins + tiles - 1) / tiles + 3) / 4 * 4 : (uint32_t)bins;
+    const bool direct = (flags & OMPRT_CFG_HIST_DIRECT) ||
+                        (tiles > kMaxBinTiles && !(flags & OMPRT_CFG_HIST_TEAM_COPY));
+    if (direct) {
+        Workspace* ws = nullptr;
+        if (omprt_status st = workspace_get(stream, 1, &ws)) return st;
+        auto launch = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, dim3((unsigned)teams), dim3(threads), 0, stream, d_keys, n,
+                               (uint32_t)bins, d_hist, ws->status());
+        };
+        switch (unroll) {
+            case 1: launch(histogram_direct_kernel<1>); break;
+            case 2: launch(histogram_direct_kernel<2>); break;
+            default: launch(histogram_direct_kernel<4>); break;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "histogram launch: %s", hipGetErrorString(e));
+        return OMPRT_OK;
+    }
     const bool in_lds = tiles <= kMaxBinTiles;
     if (!in_lds) {
         tiles = 1;

@@ -1,7 +1,9 @@
 """GPU parity of the histogram reduction (reduction(+: hist[0:bins]) with
 hist[key[i]] += 1) against the oracle, exact: bin counts from 1 to 2^20
-(team copies in LDS; ranges of bins, 2 to 16 of them, each in LDS; past
-16 x 16 256 bins, copies in the global pool), uniform and
+(team copies in LDS; ranges of bins, 2 to 32 of them, each in LDS; past
+32 x 16 256 bins, atomics on hist itself by default, or team copies in the
+global pool on request; atomics on hist for any bin count on request),
+uniform and
 single-key (fully contended) inputs, an incoming histogram taking part,
 keys out of range (skipped and flagged), several launch configurations and
 repeated launches."""
@@ -13,7 +15,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-BINS = [1, 7, 256, 4096, 16256, 16257, 100000, 260096, 260097, 1 << 20]
+BINS = [1, 7, 256, 4096, 16256, 16257, 100000, 260096, 520192, 520193, 1 << 20]
 SIZES = [1, 1000, (1 << 20) | 5]
 
 
@@ -34,6 +36,23 @@ def test_uniform_keys(gpu_lib, bins):
         want, sk = oracle.histogram(keys, bins, hist=h0)
         assert sk == 0
         assert np.array_equal(run(gpu_lib, keys, bins, h0), want)
+
+
+@pytest.mark.parametrize("flag", ["HIST_TEAM_COPY", "HIST_DIRECT"])
+@pytest.mark.parametrize("bins", [7, 16257, 520193, 1 << 20])
+def test_forced_strategies(gpu_lib, flag, bins):
+    """Team copies from the global pool (team-shared allocation falling back past LDS) and
+    atomics on hist, each forced where the default would choose otherwise."""
+    g = np.random.Generator(np.random.PCG64(bins + 11))
+    cfg = {"flags": getattr(gpu_lib, "CFG_" + flag)}
+    for n in (1, 1000, 300001):
+        keys = g.integers(0, bins, n).astype(np.int32)
+        h0 = g.integers(-1000, 1000, bins).astype(np.int32)
+        want, _ = oracle.histogram(keys, bins, hist=h0)
+        assert np.array_equal(run(gpu_lib, keys, bins, h0, cfg), want), (flag, bins, n)
+    same = np.full(100003, bins // 2, dtype=np.int32)      # every key on one bin
+    want, _ = oracle.histogram(same, bins)
+    assert np.array_equal(run(gpu_lib, same, bins, np.zeros(bins), cfg), want)
 
 
 @pytest.mark.parametrize("cfg", [{"teams": 1}, {"teams": 4096, "threads": 64}, {"unroll": 1},
@@ -67,6 +86,15 @@ def test_out_of_range_keys_flagged(gpu_lib):
     with torch.cuda.stream(s):
         om.workspace_reset()
     assert om.workspace_status(stream=s) == 0
+    # the atomic strategy flags them the same way
+    with torch.cuda.stream(s):
+        h.zero_()
+        om.histogram(k, 100, h, config={"flags": om.CFG_HIST_DIRECT})
+    s.synchronize()
+    assert np.array_equal(h.cpu().numpy(), want)
+    assert om.workspace_status(stream=s) & 4
+    with torch.cuda.stream(s):
+        om.workspace_reset()
 
 
 def test_repeated_launches_accumulate(gpu_lib):
