@@ -222,19 +222,20 @@ extern "C" omprt_status omprt_generic_power(const float* d_diag, float* d_v, int
     if ((lb >= vb && lb < vb + nb) || (lb >= db && lb < db + nb))
         return fail(OMPRT_ERR_INVALID, "lambda lies inside diag or v");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    if (teams != 1) {
+    // default: one team while a team's share of the data stays small; then
+    // one team per 8 elements a thread, up to one team per CU
+    const int64_t want = teams == 0 ? n / ((int64_t)threads * 8) : teams;
+    if (want <= 1) {
+        teams = 1;
+    } else {
         int maxco = 0;
         if (omprt_status st = coresident_teams(threads, &maxco)) return st;
         const int limit = std::min(maxco, kMaxGenericTeams);
-        if (teams == 0) {
-            // one team while a team's share of the data stays small; then one
-            // more team per 8 elements a thread, up to one team per CU
-            const int64_t want = n / ((int64_t)threads * 8);
+        if (teams == 0)
             teams = (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min(limit, device_cus())));
-        } else if (teams > limit) {
+        else if (teams > limit)
             return fail(OMPRT_ERR_INVALID, "teams %d: at most %d teams of %d threads can be resident "
                         "at once here", teams, limit, threads);
-        }
     }
     hipError_t e;
     if (teams == 1) {
