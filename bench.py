@@ -107,6 +107,23 @@ def _time_us(fn, torch, reps=5, inner=1):
     return best
 
 
+def bench_teams_curve(om, torch, f, i):
+    """GB/s of the fp32 and int64 sums over the benchmark's 2^28 inputs against the team
+    count, 1 to 2048 teams of 256 threads (static default schedule, built-in vector width
+    and unroll), and the runtime's default launch."""
+    _log("reduction GB/s against the team count")
+    out = {}
+    for name, data in (("fp32_sum", f), ("int64_sum", i)):
+        x = torch.zeros(1, dtype=data.dtype, device="cuda")
+        row = {}
+        for t in [1 << k for k in range(12)] + [0]:
+            cfg = {"teams": t, "threads": 256 if t else 0, "flags": om.CFG_NO_MODEL}
+            us = _time_us(lambda: om.reduce(data, "sum", x, config=cfg), torch, reps=3)
+            row[f"T={t}" if t else "default"] = round(data.numel() * data.element_size() / us / 1e3, 1)
+        out[name] = row
+    return out
+
+
 def bench_axpy(om, torch):
     """AXPY + sum worksharing body over 2^26 fp32: chunk {0,1,64,1024} x teams x threads.
 
@@ -823,6 +840,10 @@ def main():
     refs["torch_sum_fp32_gb_s"] = round(f.numel() * 4 / us / 1e3, 1)
     us = _time_us(lambda: torch.amax(f), torch)
     refs["torch_amax_fp32_gb_s"] = round(f.numel() * 4 / us / 1e3, 1)
+    dst = torch.empty_like(f)
+    us = _time_us(lambda: dst.copy_(f), torch)
+    refs["torch_copy_fp32_gb_s"] = round(2 * f.numel() * 4 / us / 1e3, 1)   # read + write
+    del dst
     roofline["int64_sum_vs_torch_sum"] = round(achieved / refs["torch_sum_int64_gb_s"], 3)
 
     cpu, parity = None, None
@@ -839,6 +860,7 @@ def main():
 
     extra = {}
     if not args.no_extras:
+        extra["teams_curve"] = bench_teams_curve(om, torch, f, i)
         del f, i
         torch.cuda.empty_cache()
         extra["axpy"] = bench_axpy(om, torch)
