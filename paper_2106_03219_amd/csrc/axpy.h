@@ -16,8 +16,8 @@ __device__ __forceinline__ void axpy_elem(float a, const float* __restrict__ x,
 
 // Elements [lo, lo + cnt), 1 <= cnt <= B, as one batch whose loads issue
 // together (one element at a time, each would wait out a memory latency):
-// the missing ones repeat element lo + cnt - 1 -- loaded before any store of
-// the batch, so the repeated stores write the same value -- and add zero.
+// the missing ones load element lo + cnt - 1 again and add zero; only the
+// real ones are stored.
 template <int B>
 __device__ __forceinline__ void axpy_batch(float a, const float* __restrict__ x,
                                            float* __restrict__ y, int64_t lo, int64_t cnt,
@@ -31,9 +31,14 @@ __device__ __forceinline__ void axpy_batch(float a, const float* __restrict__ x,
         yy[u] = y[ii[u]];
     }
 #pragma unroll
-    for (int u = 0; u < B; ++u) {
-        yy[u] = __builtin_fmaf(a, xx[u], yy[u]);
-        y[ii[u]] = yy[u];
+    for (int u = 0; u < B; ++u) yy[u] = __builtin_fmaf(a, xx[u], yy[u]);
+    if (cnt == B) {   // a full batch stores unpredicated (measured faster for chunks of 4)
+#pragma unroll
+        for (int u = 0; u < B; ++u) y[ii[u]] = yy[u];
+    } else {          // the repeats would store the same value again
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (u < cnt) y[ii[u]] = yy[u];
     }
 #pragma unroll
     for (int u = 0; u < B; ++u) comp_add(acc, u < cnt ? yy[u] : 0.0f);
@@ -47,7 +52,7 @@ __device__ __forceinline__ void axpy_elems(float a, const float* __restrict__ x,
 }
 
 // Vectors [j, j + cnt), 1 <= cnt <= 8, of 16-byte aligned x and y, as one
-// batch (missing vectors repeat the last one, as in axpy_batch).
+// batch (missing vectors load the last one again, as in axpy_batch).
 __device__ __forceinline__ void axpy_vbatch(float a, const float4* __restrict__ xv,
                                             float4* __restrict__ yv, int64_t j, int64_t cnt,
                                             ff_t& acc) {
@@ -66,7 +71,7 @@ __device__ __forceinline__ void axpy_vbatch(float a, const float4* __restrict__ 
         yy[u].y = __builtin_fmaf(a, xx[u].y, yy[u].y);
         yy[u].z = __builtin_fmaf(a, xx[u].z, yy[u].z);
         yy[u].w = __builtin_fmaf(a, xx[u].w, yy[u].w);
-        yv[jj[u]] = yy[u];
+        if (u < cnt) yv[jj[u]] = yy[u];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -140,18 +145,15 @@ __device__ __forceinline__ void axpy_range(float a, const float* __restrict__ x,
             vy[u].z = __builtin_fmaf(a, vx[u].z, vy[u].z);
             vy[u].w = __builtin_fmaf(a, vx[u].w, vy[u].w);
         }
-        if (head) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) y[ei[u]] = ey[u];
-        }
-        if (tail) {
+        for (int u = 0; u < 4; ++u)
+            if (u < head) y[ei[u]] = ey[u];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) y[ei[4 + u]] = ey[4 + u];
-        }
-        if (jh) {
+        for (int u = 0; u < 4; ++u)
+            if (u < tail) y[ei[4 + u]] = ey[4 + u];
 #pragma unroll
-            for (int u = 0; u < U; ++u) yv[vj[u]] = vy[u];
-        }
+        for (int u = 0; u < U; ++u)
+            if (u < jh) yv[vj[u]] = vy[u];
 #pragma unroll
         for (int u = 0; u < 4; ++u) comp_add(acc, u < head ? ey[u] : 0.0f);
 #pragma unroll
