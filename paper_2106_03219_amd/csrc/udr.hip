@@ -8,8 +8,10 @@
 // The generated kernel is the plain reduction's pipeline with the user's
 // type: teams take the balanced block bal(n, T, k) of the input; lanes read
 // interleaved 16-byte vectors, four in flight, and a lane folds its elements
-// into its private copy with the user's loop body in increasing position
-// (the head before 16-byte alignment and the tail one element a lane);
+// with the user's loop body into up to four private copies (one per element
+// slot of a vector for types up to 32 bytes, each in increasing position;
+// the head before 16-byte alignment and the tail one element a lane), which
+// it then combines;
 // private copies meet through
 // the wave / team tree and the tagged last-team combine (a type of up to
 // 64 bytes spans up to four cross-team slots); the last team combines the
@@ -107,15 +109,23 @@ extern "C" __global__ __launch_bounds__(1024) void omprt_udr_kernel(
     const int64_t tid = threadIdx.x;
     const uint32_t epoch = T > 1 ? read_epoch(ct.epoch) : 0u;
     const Range blk = bal_share(n, T, blockIdx.x);
-    R::Acc a = R::identity();
+    // A lane keeps one private copy per element slot of a vector (at most
+    // four), each folding its elements in increasing position, and combines
+    // them at the end: independent update chains instead of one (an exact
+    // three-field int32 reduction: 5.2 -> 6.5 TB/s).  Types over 32 bytes keep
+    // one copy: several copies of a 64-byte type with an indexed member went
+    // to scratch memory (6.7 -> 0.95 TB/s).
+    constexpr int NA = sizeof(R::Acc) > 32 ? 1 : PER < 4 ? PER : 4;
+    R::Acc acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = R::identity();
     if (blk.lo < blk.hi) {
-        // a lane meets its elements in increasing position: the head up to
-        // 16-byte alignment, its vectors (lanes interleaved), the tail
+        // the head up to 16-byte alignment, the vectors (lanes interleaved), the tail
         const int64_t lo = blk.lo, hi = blk.hi;
         const uintptr_t mis = reinterpret_cast<uintptr_t>(in + lo) & 15;
         int64_t head = (int64_t)(((16 - mis) & 15) / sizeof(typename D::S));
         if (head > hi - lo) head = hi - lo;
-        if (tid < head) R::elem(a, D::from(in[lo + tid]), lo + tid);
+        if (tid < head) R::elem(acc[0], D::from(in[lo + tid]), lo + tid);
         const int64_t p0 = lo + head;
         const int64_t nv = (hi - p0) / PER;
         const Vec* __restrict__ vp = reinterpret_cast<const Vec*>(in + p0);
@@ -128,18 +138,21 @@ extern "C" __global__ __launch_bounds__(1024) void omprt_udr_kernel(
             for (int u = 0; u < U; ++u) {
                 const int64_t i0 = p0 + (v + u * P) * PER;
 #pragma unroll
-                for (int e = 0; e < PER; ++e) R::elem(a, L::get(r[u], e), i0 + e);
+                for (int e = 0; e < PER; ++e) R::elem(acc[e % NA], L::get(r[u], e), i0 + e);
             }
         }
         for (; v < nv; v += P) {
             const Vec r = L::load(vp + v);
             const int64_t i0 = p0 + v * PER;
 #pragma unroll
-            for (int e = 0; e < PER; ++e) R::elem(a, L::get(r, e), i0 + e);
+            for (int e = 0; e < PER; ++e) R::elem(acc[e % NA], L::get(r, e), i0 + e);
         }
         const int64_t t0 = p0 + nv * PER;
-        if (tid < hi - t0) R::elem(a, D::from(in[t0 + tid]), t0 + tid);
+        if (tid < hi - t0) R::elem(acc[0], D::from(in[t0 + tid]), t0 + tid);
     }
+    R::Acc a = acc[0];
+#pragma unroll
+    for (int q = 1; q < NA; ++q) a = R::combine(a, acc[q]);
     a = team_reduce<R>(a, lds);
     R::Acc c = a;
     if (T > 1) {
