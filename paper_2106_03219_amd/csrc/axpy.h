@@ -83,6 +83,37 @@ __device__ __forceinline__ void axpy_vbatch(float a, const float4* __restrict__ 
     }
 }
 
+// A chunk [lo, hi) of at most 16 iterations that is whole 16-byte vectors of
+// co-aligned x and y (chunks of 4 to 16 on an aligned block): one vector, or
+// one batch of up to four, without the edge handling of longer runs --
+// neighbouring lanes' chunks are adjacent, so a wave's loads cover whole
+// lines.  Returns false (nothing done) for any other chunk.
+__device__ __forceinline__ bool axpy_short_run(float a, const float* __restrict__ x,
+                                               float* __restrict__ y, int64_t lo, int64_t hi,
+                                               ff_t& acc) {
+    const int64_t len = hi - lo;
+    if (len < 4 || len > 16 || (len & 3) ||
+        ((reinterpret_cast<uintptr_t>(x + lo) | reinterpret_cast<uintptr_t>(y + lo)) & 15))
+        return false;
+    if (len == 4) {
+        const float4 xx = *reinterpret_cast<const float4*>(x + lo);
+        float4 yy = *reinterpret_cast<const float4*>(y + lo);
+        yy.x = __builtin_fmaf(a, xx.x, yy.x);
+        yy.y = __builtin_fmaf(a, xx.y, yy.y);
+        yy.z = __builtin_fmaf(a, xx.z, yy.z);
+        yy.w = __builtin_fmaf(a, xx.w, yy.w);
+        *reinterpret_cast<float4*>(y + lo) = yy;
+        comp_add(acc, yy.x);
+        comp_add(acc, yy.y);
+        comp_add(acc, yy.z);
+        comp_add(acc, yy.w);
+    } else {
+        axpy_vbatch(a, reinterpret_cast<const float4*>(x + lo), reinterpret_cast<float4*>(y + lo), 0,
+                    len / 4, acc);
+    }
+    return true;
+}
+
 // One chunk [lo, hi) of the calling thread.  Where x and y are co-aligned:
 // up to three elements to 16-byte alignment, vectors up to a 128-byte line
 // boundary and the last up to three elements go first, as one batch; then

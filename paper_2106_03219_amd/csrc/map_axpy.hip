@@ -69,7 +69,8 @@ __global__ __launch_bounds__(1024) void axpy_sum_kernel(float a, const float* __
             const int64_t nc = thread_nchunks(m, P, c, t);
             for (int64_t j = 0; j < nc; ++j) {
                 const Range ch = thread_chunk(blk.lo, m, P, c, t, j);
-                axpy_range(a, x, y, ch.lo, ch.hi, acc);
+                if (c > 16 || !axpy_short_run(a, x, y, ch.lo, ch.hi, acc))
+                    axpy_range(a, x, y, ch.lo, ch.hi, acc);
             }
         }
     }

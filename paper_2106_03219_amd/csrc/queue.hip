@@ -184,7 +184,8 @@ __global__ __launch_bounds__(512) void queue_axpy_kernel(QueueCfg qc, float a,
                         const int64_t tk = g.first + (int64_t)j * g.stride;
                         if (tk >= bq.nchunks) break;
                         const Range ch = bq.chunk(tk);
-                        axpy_range(a, xb, yb, ch.lo, ch.hi, acc);
+                        if (ch.hi - ch.lo > 16 || !axpy_short_run(a, xb, yb, ch.lo, ch.hi, acc))
+                            axpy_range(a, xb, yb, ch.lo, ch.hi, acc);
                     }
                 }
             }

@@ -92,7 +92,8 @@ __global__ __launch_bounds__(1024) void region_axpy_then_sum_kernel(
             const int64_t nc = thread_nchunks(m, P, c1, t);
             for (int64_t j = 0; j < nc; ++j) {
                 const Range ch = thread_chunk(blk.lo, m, P, c1, t, j);
-                axpy_range(a, x, y, ch.lo, ch.hi, unused);
+                if (c1 > 16 || !axpy_short_run(a, x, y, ch.lo, ch.hi, unused))
+                    axpy_range(a, x, y, ch.lo, ch.hi, unused);
             }
         }
     }
