@@ -110,7 +110,8 @@ def _time_us(fn, torch, reps=5, inner=1):
 def bench_teams_curve(om, torch, f, i):
     """GB/s of the fp32 and int64 sums over the benchmark's 2^28 inputs against the team
     count, 1 to 2048 teams of 256 threads (static default schedule, built-in vector width
-    and unroll), and the runtime's default launch."""
+    and unroll), the runtime's default launch, and that launch with every thread reducing
+    exactly its schedule(static) run (EXACT_THREAD_MAP)."""
     _log("reduction GB/s against the team count")
     out = {}
     for name, data in (("fp32_sum", f), ("int64_sum", i)):
@@ -120,6 +121,10 @@ def bench_teams_curve(om, torch, f, i):
             cfg = {"teams": t, "threads": 256 if t else 0, "flags": om.CFG_NO_MODEL}
             us = _time_us(lambda: om.reduce(data, "sum", x, config=cfg), torch, reps=3)
             row[f"T={t}" if t else "default"] = round(data.numel() * data.element_size() / us / 1e3, 1)
+        # the same default launch with every thread reducing exactly its static run
+        cfg = {"flags": om.CFG_NO_MODEL | om.CFG_EXACT_THREAD_MAP}
+        us = _time_us(lambda: om.reduce(data, "sum", x, config=cfg), torch, reps=3)
+        row["default_exact_thread_map"] = round(data.numel() * data.element_size() / us / 1e3, 1)
         out[name] = row
     return out
 

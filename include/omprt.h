@@ -114,6 +114,12 @@ typedef struct {
                                           atomics on hist */
 #define OMPRT_CFG_HIST_DIRECT 0x8u     /* histogram: atomics on hist for any bin
                                           count (no team copy) */
+#define OMPRT_CFG_EXACT_THREAD_MAP 0x10u /* omprt_reduce (sum / max / min): every
+                                            thread reduces exactly its
+                                            schedule(static) run of the team's
+                                            block, instead of the team's lanes
+                                            reading interleaved vectors (for
+                                            comparison) */
 
 /* One independent reduction of a batch.  x follows omprt_reduce. */
 typedef struct {
@@ -176,7 +182,9 @@ omprt_status omprt_static_map(const omprt_sched *s, int32_t *d_owner,
  * in compensated fp64 likewise.  n == 0 leaves *d_x unchanged.  The result is deterministic for a
  * fixed (n, configuration).  Teams follow the static distribute schedule
  * (team k reduces the balanced block bal(n, T, k)); inside a team lanes read
- * interleaved vectors, which no reduction body can observe.  The cross-team
+ * interleaved vectors, which no reduction body can observe (cfg->flags
+ * OMPRT_CFG_EXACT_THREAD_MAP makes every thread reduce exactly its
+ * schedule(static) run instead; sum, max and min).  The cross-team
  * combine is done by the last team to finish, found with a wrap-around
  * atomic increment that leaves its counter at 0.
  * d_in needs only element alignment.  cfg may be NULL.

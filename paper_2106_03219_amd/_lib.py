@@ -19,6 +19,7 @@ CFG_NO_MODEL = 0x1
 CFG_STATIC_TILES = 0x2
 CFG_HIST_TEAM_COPY = 0x4
 CFG_HIST_DIRECT = 0x8
+CFG_EXACT_THREAD_MAP = 0x10
 
 
 class Sched(ctypes.Structure):

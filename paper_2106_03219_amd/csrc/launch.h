@@ -31,6 +31,11 @@ hipError_t launch_static_map(int64_t n, int teams, int threads, int64_t dist_chu
                              int64_t chunk, int32_t* owner, uint32_t* count,
                              hipStream_t stream);
 
+// The plain reduction (sum, max, min) with every thread reducing exactly its
+// schedule(static) run of the team's block (exact.hip).
+hipError_t launch_reduce_exact(int dtype, int op, const void* in, int64_t n, void* x, int teams,
+                               int threads, const CrossTeamArgs& ct, hipStream_t stream);
+
 // y <- fmaf(a, x, y) with the exact static mapping, fused compensated sum.
 hipError_t launch_axpy_sum(float a, const float* x, float* y, float* sum, int64_t n,
                            int teams, int threads, int64_t dist_chunk, int64_t chunk,

@@ -357,8 +357,13 @@ extern "C" omprt_status omprt_reduce(const void* d_in, int64_t n, int32_t dtype,
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     Workspace* ws = nullptr;
     if (omprt_status st = workspace_get(stream, lc.teams, &ws)) return st;
-    const hipError_t e = launch_reduce(dtype, op, lc.vec, lc.unroll, d_in, n, d_x, lc.teams,
-                                       lc.threads, ws->cross(), stream);
+    const bool exact = cfg && (cfg->flags & OMPRT_CFG_EXACT_THREAD_MAP);
+    if (exact && op > OMPRT_MIN)
+        return fail(OMPRT_ERR_UNSUPPORTED, "EXACT_THREAD_MAP takes sum, max and min");
+    const hipError_t e =
+        exact ? launch_reduce_exact(dtype, op, d_in, n, d_x, lc.teams, lc.threads, ws->cross(), stream)
+              : launch_reduce(dtype, op, lc.vec, lc.unroll, d_in, n, d_x, lc.teams, lc.threads,
+                              ws->cross(), stream);
     if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "reduce launch: %s", hipGetErrorString(e));
     return OMPRT_OK;
 }

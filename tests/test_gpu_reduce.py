@@ -291,3 +291,41 @@ def test_max_sizes(gpu_lib):
     om.reduce(to_device(a, synth.I64), "sum", y, config={"teams": 65535, "threads": 64})
     torch.cuda.synchronize()
     assert y.item() == ref
+
+
+# ---------------------------------------------------------------- exact thread map
+
+@pytest.mark.parametrize("dtype", [synth.I32, synth.I64, synth.F32, synth.F64, synth.BF16])
+def test_exact_thread_map_matches_oracle(gpu_lib, dtype):
+    """EXACT_THREAD_MAP (every thread reduces its schedule(static) run): every op on ragged
+    and misaligned sizes under several team shapes, against the oracle; integers, max and min
+    also equal to the interleaved kernel's bits."""
+    om = gpu_lib
+    flag = om.CFG_EXACT_THREAD_MAP
+    for k, n in enumerate([1, 3, 64, 1000, 4099, 65537, (1 << 20) + 7]):
+        host = synth.host(dtype, n + 1, 900 + k)
+        for op in OPS:
+            for cfg in ({"teams": 1, "threads": 64}, {"teams": 7, "threads": 256},
+                        {"teams": 300, "threads": 1024}, {}):
+                got = _reduce_and_check(om, host, dtype, op, identity(dtype, op),
+                                        config=dict(cfg, flags=flag), offset=1,
+                                        what=(n, op, cfg))
+                if dtype in (synth.I32, synth.I64) or op != "sum":
+                    plain = _reduce_and_check(om, host, dtype, op, identity(dtype, op),
+                                              config=cfg or None, offset=1)
+                    assert got == plain, (n, op, cfg, got, plain)
+    with pytest.raises(om.OmprtError):
+        x = torch.zeros(1, dtype=torch.int32, device="cuda")
+        om.reduce(to_device(synth.host(synth.I32, 10, 1), synth.I32), "prod", x,
+                  config={"flags": flag})
+
+
+def test_exact_thread_map_2pow28(gpu_lib, big_inputs):
+    om = gpu_lib
+    f, i, refs = big_inputs
+    for dev, dtype, key in ((f, synth.F32, "f32"), (i, synth.I64, "i64")):
+        x = x_tensor(dtype, "sum", 0)
+        om.reduce(dev, "sum", x, config={"flags": om.CFG_EXACT_THREAD_MAP})
+        torch.cuda.synchronize()
+        ref, sabs = refs[(key, "sum")]
+        check_value(x_value(x), ref, sabs, dtype, "sum", "exact 2^28")
