@@ -850,6 +850,7 @@ def main():
     refs["torch_copy_fp32_gb_s"] = round(2 * f.numel() * 4 / us / 1e3, 1)   # read + write
     del dst
     roofline["int64_sum_vs_torch_sum"] = round(achieved / refs["torch_sum_int64_gb_s"], 3)
+    roofline["int64_sum_vs_torch_copy"] = round(achieved / refs["torch_copy_fp32_gb_s"], 3)
 
     cpu, parity = None, None
     if not args.no_cpu_baseline:
