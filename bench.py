@@ -778,7 +778,7 @@ def main():
         return
 
     if args.only_hist:
-        bins = (256, 4096, 16256, 16257, 65536, 260096, 520192, 520193, 1 << 20, 1 << 24)
+        bins = (256, 4096, 16257, 40704, 40705, 100000, 260096, 1 << 20, 1302529, 1 << 24)
         print(json.dumps({"histogram": bench_hist(om, torch, bins)}), flush=True)
         return
 

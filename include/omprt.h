@@ -201,11 +201,11 @@ omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
  * [0, bins) are not counted and set bit 4 of the stream's workspace status.
  * Each team keeps a team-shared copy of the histogram, taken with the
  * runtime's team-shared allocation, counts its balanced block of keys into
- * it with atomic adds and adds the copy into d_hist.  Up to 16 256 bins
- * the copy is in LDS; up to 32 times that, the bins are cut into ranges of
- * that size, each team counting the keys of one range (every key is read
- * once per range); beyond, every key is an atomic add on d_hist itself (no
- * copy).  cfg->flags OMPRT_CFG_HIST_TEAM_COPY keeps team copies past the
+ * it with atomic adds and adds the copy into d_hist.  Up to the LDS one
+ * workgroup may take (40 704 bins on gfx950's 160 KiB) the copy is in LDS;
+ * up to 32 times that, the bins are cut into ranges of that size, each team
+ * counting the keys of one range (every key is read once per range);
+ * beyond, every key is an atomic add on d_hist itself (no copy).  cfg->flags OMPRT_CFG_HIST_TEAM_COPY keeps team copies past the
  * ranges, each a slice of a global pool the library keeps per stream
  * (team-shared allocation falling back from LDS; atomics at L2);
  * OMPRT_CFG_HIST_DIRECT takes atomics on d_hist for any bin count.  cfg:

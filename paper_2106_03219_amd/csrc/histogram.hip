@@ -243,10 +243,27 @@ void histogram_finalize() {
     g_pools.clear();
 }
 
-constexpr uint32_t kHistLds = 64 * 1024 - 512;   // dynamic LDS per team
+// Dynamic LDS a team's copy may take: the device's LDS per workgroup (160 KiB
+// on gfx950: 40 704 bins) less 1 KiB of room for the kernel's static LDS.
+constexpr uint32_t kHistStaticLds = 1024;
+static uint32_t hist_lds_cap() {
+    static uint32_t cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024 - kHistStaticLds;
+    if (!cached[dev]) {
+        int bytes = 0;
+        if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess ||
+            bytes < 64 * 1024)
+            bytes = 64 * 1024;
+        cached[dev] = (uint32_t)bytes - kHistStaticLds;
+    }
+    return cached[dev];
+}
 // Bin ranges before atomics on hist: a key is read once per range, so ranges
-// cost about 1.6 T keys/s / ranges at 2^28 keys (2: 808 G/s, 16: 125 G/s)
-// against about 27 G keys/s for atomics on hist; 32 ranges keep a 2x margin.
+// cost about 1.6 T keys/s / ranges at 2^28 keys (2: 808 G/s, 16: 125 G/s with
+// 64 KiB ranges) against about 27 G keys/s for atomics on hist; 32 ranges
+// keep a 2x margin.
 constexpr uint32_t kMaxBinTiles = 32;
 
 }  // namespace omprt
@@ -286,7 +303,7 @@ extern "C" omprt_status omprt_histogram(const int32_t* d_keys, int64_t n, int32_
     // the keys and counts those in its range: tiles x the key traffic, at
     // LDS atomic speed); past that, atomics on hist, or on request team
     // copies in the global pool (atomics at L2, then a merge).
-    constexpr uint32_t lds_bins = kHistLds / 4 / 4 * 4;
+    const uint32_t lds_bins = hist_lds_cap() / 4 / 4 * 4;
     uint32_t tiles = (uint32_t)((bins + lds_bins - 1) / lds_bins);
     uint32_t tile_bins = tiles > 1 ? (uint32_t)((bins + tiles - 1) / tiles + 3) / 4 * 4 : (uint32_t)bins;
     const bool direct = (flags & OMPRT_CFG_HIST_DIRECT) ||
@@ -325,7 +342,12 @@ extern "C" omprt_status omprt_histogram(const int32_t* d_keys, int64_t n, int32_
     Workspace* ws = nullptr;
     if (omprt_status st = workspace_get(stream, 1, &ws)) return st;
     const uint32_t lds = in_lds ? (uint32_t)hbytes : 0u;
+    hipError_t attr = hipSuccess;
     auto launch = [&](auto kernel) {
+        if (lds > 64 * 1024)   // past the default dynamic LDS limit: ask for it
+            attr = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (attr != hipSuccess) return;
         hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), lds, stream, d_keys, n,
                            (uint32_t)bins, tiles, tile_bins, d_hist, static_cast<char*>(pool),
                            per_team, lds, ws->status());
@@ -335,6 +357,8 @@ extern "C" omprt_status omprt_histogram(const int32_t* d_keys, int64_t n, int32_
         case 2: launch(histogram_kernel<2>); break;
         default: launch(histogram_kernel<4>); break;
     }
+    if (attr != hipSuccess)
+        return fail(OMPRT_ERR_DEVICE, "histogram: %u bytes of LDS: %s", lds, hipGetErrorString(attr));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "histogram launch: %s", hipGetErrorString(e));
     return OMPRT_OK;

@@ -1,7 +1,8 @@
 """GPU parity of the histogram reduction (reduction(+: hist[0:bins]) with
-hist[key[i]] += 1) against the oracle, exact: bin counts from 1 to 2^20
-(team copies in LDS; ranges of bins, 2 to 32 of them, each in LDS; past
-32 x 16 256 bins, atomics on hist itself by default, or team copies in the
+hist[key[i]] += 1) against the oracle, exact: bin counts from 1 to 1 400 000
+(team copies in LDS -- up to 40 704 bins with gfx950's 160 KiB a workgroup;
+ranges of bins, 2 to 32 of them, each in LDS; past 32 ranges, atomics on
+hist itself by default, or team copies in the
 global pool on request; atomics on hist for any bin count on request),
 uniform and
 single-key (fully contended) inputs, an incoming histogram taking part,
@@ -15,7 +16,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-BINS = [1, 7, 256, 4096, 16256, 16257, 100000, 260096, 520192, 520193, 1 << 20]
+BINS = [1, 7, 256, 4096, 16256, 16257, 40704, 40705, 100000, 520193, 1 << 20, 1302528, 1302529]
 SIZES = [1, 1000, (1 << 20) | 5]
 
 
@@ -39,12 +40,15 @@ def test_uniform_keys(gpu_lib, bins):
 
 
 @pytest.mark.parametrize("flag", ["HIST_TEAM_COPY", "HIST_DIRECT"])
-@pytest.mark.parametrize("bins", [7, 16257, 520193, 1 << 20])
+@pytest.mark.parametrize("bins", [7, 16257, 1 << 20, 1400000])
 def test_forced_strategies(gpu_lib, flag, bins):
     """Team copies from the global pool (team-shared allocation falling back past LDS) and
-    atomics on hist, each forced where the default would choose otherwise."""
+    atomics on hist, each forced where the default would choose otherwise (the pool holds a
+    full copy per team: 16 teams keep it small)."""
     g = np.random.Generator(np.random.PCG64(bins + 11))
     cfg = {"flags": getattr(gpu_lib, "CFG_" + flag)}
+    if flag == "HIST_TEAM_COPY":
+        cfg["teams"] = 16
     for n in (1, 1000, 300001):
         keys = g.integers(0, bins, n).astype(np.int32)
         h0 = g.integers(-1000, 1000, bins).astype(np.int32)
