@@ -235,13 +235,15 @@ omprt_status omprt_histogram(const int32_t *d_keys, int64_t n, int32_t bins,
  * block bal(n, T, k) of both loops and every team running the sequential
  * code on the same s, which reaches all teams by an all-gather of team
  * partials through the stream's workspace (a partial that never arrives
- * sets bit 1 of the workspace status, see omprt_workspace_status); 0 = one
- * team while n <= 8 * threads, then one team per 8 * threads elements, up
- * to one per compute unit.  At most 512 teams and no more than fit at once
+ * sets bit 1 of the workspace status, see omprt_workspace_status); 0 = the
+ * runtime's choice: with threads 0, one team of 512 threads up to 8192
+ * elements, else one team of 256 threads per 2048 elements; with threads
+ * given, one team per 8 * threads elements; at most one per compute unit.  At most 512 teams and no more than fit at once
  * (OMPRT_ERR_INVALID otherwise); OMPRT_ERR_UNSUPPORTED if the device has no
  * cooperative launch.  For fixed (teams, threads) the results are
  * deterministic (the sum's rounding follows its combination order).
- * threads: 64..1024, a multiple of 64; 0 = 1024.  n 1..2^32, iters >= 1;
+ * threads: 64..1024, a multiple of 64; 0 = the runtime's choice (512 for
+ * one team, 256 for several).  n 1..2^32, iters >= 1;
  * d_diag and d_v must not overlap, and d_lambda lies in neither.  One
  * kernel launch on hip_stream; invalid arguments return OMPRT_ERR_INVALID
  * before anything is launched.

@@ -209,7 +209,11 @@ extern "C" omprt_status omprt_generic_power(const float* d_diag, float* d_v, int
         return fail(OMPRT_ERR_INVALID, "n = %lld outside 1..2^32", (long long)n);
     if (iters < 1) return fail(OMPRT_ERR_INVALID, "iters %d < 1", iters);
     if (teams < 0) return fail(OMPRT_ERR_INVALID, "teams %d < 0", teams);
-    if (threads == 0) threads = 1024;
+    // default shape (measured at 2^10..2^20 elements, 100 steps): one team of
+    // 512 threads while the loops are short, else teams of 256 threads, one
+    // per 2048 elements, up to one per CU
+    const bool auto_threads = threads == 0;
+    if (auto_threads) threads = (teams == 1 || (teams == 0 && n <= 8192)) ? 512 : 256;
     if (threads < 64 || threads > 1024 || threads % 64)
         return fail(OMPRT_ERR_INVALID, "threads %d: 64..1024, a multiple of 64", threads);
     if (!d_diag || !d_v || !d_lambda) return fail(OMPRT_ERR_INVALID, "NULL pointer");
@@ -222,9 +226,9 @@ extern "C" omprt_status omprt_generic_power(const float* d_diag, float* d_v, int
     if ((lb >= vb && lb < vb + nb) || (lb >= db && lb < db + nb))
         return fail(OMPRT_ERR_INVALID, "lambda lies inside diag or v");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    // default: one team while a team's share of the data stays small; then
-    // one team per 8 elements a thread, up to one team per CU
-    const int64_t want = teams == 0 ? n / ((int64_t)threads * 8) : teams;
+    const int64_t want = teams != 0  ? teams
+                         : auto_threads ? (n <= 8192 ? 1 : n / 2048)
+                                        : n / ((int64_t)threads * 8);
     if (want <= 1) {
         teams = 1;
     } else {
