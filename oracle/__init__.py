@@ -23,6 +23,9 @@ statement of each):
 * :func:`reduce_loc` -- maxloc / minloc (value and position, ties to the
   smaller position).
 * :func:`axpy_sum` -- the AXPY worksharing body with fused fmaf.
+* :func:`fold_prefixes`, :func:`axpy_prefix_sums` -- the same sum / max / min
+  folds and AXPY sums read out at several prefix lengths of one array in one
+  pass (the autotuner's instances are prefixes of shared buffers).
 * :func:`udr_fold`, :func:`moments` -- a user-defined reduction (declare
   reduction) by its sequential definition: the private copy starts at the
   initializer, the loop body folds the elements in order, the combiner
@@ -102,6 +105,11 @@ def _load():
     lib.oracle_queue_chunks.restype = i64
     lib.oracle_team_queue.argtypes = [ctypes.c_int, i64, i64, i64, i64, i64, i64, p, p, i64]
     lib.oracle_team_queue.restype = i64
+    lib.oracle_fold_prefixes.argtypes = [p, ctypes.c_int, ctypes.c_int, ctypes.c_double, i64, p, i64,
+                                         p, p]
+    lib.oracle_fold_prefixes.restype = ctypes.c_int
+    lib.oracle_axpy_prefix_sums.argtypes = [ctypes.c_float, p, p, ctypes.c_double, p, i64, p]
+    lib.oracle_axpy_prefix_sums.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -170,6 +178,62 @@ def reduce_fp(a: np.ndarray, op: str, x: float = 0.0, bf16: bool = False,
     r = _load().oracle_reduce_fp(_ptr(a), a.size, dt, _OPS[op], float(x),
                                  ctypes.byref(s_abs) if want_abs else None)
     return (r, s_abs.value) if want_abs else r
+
+
+_PREFIX_DT = {np.dtype(np.int32): 0, np.dtype(np.int64): 1, np.dtype(np.float32): 2,
+              np.dtype(np.float64): 3}
+
+
+def fold_prefixes(a: np.ndarray, op: str, lens, x=None, bf16: bool = False):
+    """The sum / max / min fold of a[0..L) for every L in lens, in one pass: a list in
+    the order of lens, each what reduce_int / reduce_fp gives for that prefix with
+    the same x (default: the op's identity).  Integers as int, floats as float."""
+    a = np.ascontiguousarray(a)
+    dt = 4 if bf16 else _PREFIX_DT[a.dtype]
+    lens = np.asarray(lens, dtype=np.int64)
+    order = np.argsort(lens, kind="stable")
+    sl = np.ascontiguousarray(lens[order])
+    if sl.size and (sl[0] < 0 or sl[-1] > a.size):
+        raise ValueError("prefix length outside the array")
+    out_i = np.zeros(sl.size, np.int64)
+    out_f = np.zeros(sl.size, np.float64)
+    if dt <= 1:
+        info = np.iinfo(a.dtype)
+        xi = 0 if op == "sum" else int(info.min if op == "max" else info.max)
+        xi = xi if x is None else int(x)
+        xf = 0.0
+    else:
+        xf = 0.0 if op == "sum" else (-np.inf if op == "max" else np.inf)
+        xf = xf if x is None else float(x)
+        xi = 0
+    if _load().oracle_fold_prefixes(_ptr(a), dt, _OPS[op], xf, xi, _ptr(sl), sl.size,
+                                    _ptr(out_i), _ptr(out_f)) != 0:
+        raise ValueError("bad op or lengths")
+    res = [None] * sl.size
+    for k, j in enumerate(order):
+        res[j] = int(out_i[k]) if dt <= 1 else float(out_f[k])
+    return res
+
+
+def axpy_prefix_sums(a: float, x: np.ndarray, y: np.ndarray, lens, s_orig: float = 0.0):
+    """(y', sums): y' = fmaf(a, x, y) over the longest prefix (a new array), and for
+    every L in lens the FP64 sum of y'[0..L) from s_orig, as axpy_sum gives it."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    lens = np.asarray(lens, dtype=np.int64)
+    order = np.argsort(lens, kind="stable")
+    sl = np.ascontiguousarray(lens[order])
+    top = int(sl[-1]) if sl.size else 0
+    if top > x.size or top > y.size:
+        raise ValueError("prefix length outside the arrays")
+    y2 = np.array(y[:top], dtype=np.float32, copy=True)
+    out = np.zeros(sl.size, np.float64)
+    if _load().oracle_axpy_prefix_sums(ctypes.c_float(a), _ptr(x), _ptr(y2), float(s_orig),
+                                       _ptr(sl), sl.size, _ptr(out)) != 0:
+        raise ValueError("bad lengths")
+    sums = [0.0] * sl.size
+    for k, j in enumerate(order):
+        sums[j] = float(out[k])
+    return y2, sums
 
 
 def axpy_sum(a: float, x: np.ndarray, y: np.ndarray, s_orig: float = 0.0):

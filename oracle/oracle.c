@@ -374,6 +374,57 @@ double oracle_reduce_fp(const void *in, int64_t n, int dtype, int op,
 }
 
 /*
+ * The same folds at several prefix lengths in one pass: out[k] is what
+ * oracle_reduce_i32 / oracle_reduce_i64 (dtype 0 / 1) or oracle_reduce_fp
+ * (dtype 2 fp32, 3 fp64, 4 bf16 raw) would return for in[0..lens[k]) with
+ * the same op (sum, max or min) and x.  lens must be ascending; the fold runs
+ * over in[0..lens[nlens-1]) in index order and its running state is read out
+ * as each length is passed (integer results are returned as int64, floating
+ * ones as double).  Returns 0, or -1 for lengths that are not ascending or an
+ * op other than sum / max / min.
+ */
+int oracle_fold_prefixes(const void *in, int dtype, int op, double x_fp, int64_t x_int,
+                         const int64_t *lens, int64_t nlens, int64_t *out_int,
+                         double *out_fp)
+{
+    if (op != OR_SUM && op != OR_MAX && op != OR_MIN) return -1;
+    for (int64_t k = 1; k < nlens; k++)
+        if (lens[k] < lens[k - 1]) return -1;
+    uint64_t uacc = (uint64_t)x_int;
+    int64_t im = x_int;
+    neum acc = { x_fp, 0.0 };
+    double m = x_fp;
+    int64_t i = 0;
+    for (int64_t k = 0; k < nlens; k++) {
+        for (; i < lens[k]; i++) {
+            if (dtype == 0 || dtype == 1) {
+                int64_t v = dtype == 0 ? (int64_t)((const int32_t *)in)[i]
+                                       : ((const int64_t *)in)[i];
+                if (op == OR_SUM) uacc += (uint64_t)v;
+                else if (op == OR_MAX && v > im) im = v;
+                else if (op == OR_MIN && v < im) im = v;
+            } else {
+                double v;
+                if (dtype == 2) v = (double)((const float *)in)[i];
+                else if (dtype == 3) v = ((const double *)in)[i];
+                else v = bf16_to_double(((const uint16_t *)in)[i]);
+                if (op == OR_SUM) neum_add(&acc, v);
+                else if (op == OR_MAX) m = fmax(m, v);
+                else m = fmin(m, v);
+            }
+        }
+        if (dtype == 0) {   /* wrap in 32 bits */
+            out_int[k] = op == OR_SUM ? (int64_t)(int32_t)(uint32_t)uacc : im;
+        } else if (dtype == 1) {
+            out_int[k] = op == OR_SUM ? (int64_t)uacc : im;
+        } else {
+            out_fp[k] = op == OR_SUM ? acc.s + acc.c : m;
+        }
+    }
+    return 0;
+}
+
+/*
  * maxloc / minloc, the usual user-defined reduction (a value with its
  * position): the pairs (x_val, x_idx), (in[0], 0), ..., (in[n-1], n-1) are
  * folded with "keep the larger (op 1) or smaller (op 2) value; on equal
@@ -473,6 +524,29 @@ double oracle_axpy_sum(float a, const float *x, float *y, int64_t n,
         neum_add(&acc, (double)y[i]);
     }
     return acc.s + acc.c;
+}
+
+/*
+ * The AXPY body at several prefix lengths in one pass: y[i] <- fmaf(a, x[i],
+ * y[i]) for i < lens[nlens-1] (in place), and out[k] = the FP64 Neumaier sum
+ * of the updated y[0..lens[k]) starting from s_orig -- what oracle_axpy_sum
+ * returns over that prefix.  lens ascending; returns 0, or -1 otherwise.
+ */
+int oracle_axpy_prefix_sums(float a, const float *x, float *y, double s_orig,
+                            const int64_t *lens, int64_t nlens, double *out)
+{
+    for (int64_t k = 1; k < nlens; k++)
+        if (lens[k] < lens[k - 1]) return -1;
+    neum acc = { s_orig, 0.0 };
+    int64_t i = 0;
+    for (int64_t k = 0; k < nlens; k++) {
+        for (; i < lens[k]; i++) {
+            y[i] = fmaf(a, x[i], y[i]);
+            neum_add(&acc, (double)y[i]);
+        }
+        out[k] = acc.s + acc.c;
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
