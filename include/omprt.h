@@ -30,6 +30,14 @@
  *  - Calls on one stream are serialised by the stream.  Different streams
  *    get different workspaces, so concurrent calls on different streams do
  *    not interfere.  Two host threads must not share one stream.
+ *  - The library's own device memory (per-stream workspaces, pools, scratch,
+ *    batched plans) is never freed while in use: when a call needs a larger
+ *    buffer than the stream has, the old one is kept, unused, until
+ *    omprt_finalize, so a HIP graph a caller captured around earlier calls
+ *    stays valid however later eager calls grow the buffers.  omprt_finalize
+ *    frees everything; graphs captured before it must not be replayed after
+ *    it.  No memory is released from static destructors at process exit:
+ *    call omprt_finalize before exiting to release it explicitly.
  */
 #ifndef OMPRT_H
 #define OMPRT_H
@@ -142,6 +150,11 @@ typedef struct {
  * n-1 (the sequentially last iteration), else 0.  Pure host integer
  * arithmetic, O(1).  A thread's chunks do not in general form one
  * arithmetic progression (dist_chunk > 0 and chunk > 0), hence the index.
+ * Defining passage: the device runtime supplies the routines the compiler
+ * calls for worksharing loops (sec. 1), a lowered parallel for calling into
+ * it to divide the loop's iterations (sec. 2, opening); teams are thread
+ * blocks (sec. 3.1, "Global Shared Variables").  The chunk rules are the
+ * static schedule of the OpenMP specification that the paper implements.
  * Errors: INVALID for NULL pointers, n < 0, num_teams < 1,
  * threads_per_team outside 1..1024, negative chunks, team/thread out of
  * range, j < 0.
@@ -151,7 +164,8 @@ omprt_status omprt_for_static_bounds(const omprt_sched *s, int32_t team,
                                      int64_t *ub, int32_t *is_last);
 
 /* Number of non-empty chunks and of iterations thread `thread` of team
- * `team` executes under *s.  Same errors as omprt_for_static_bounds. */
+ * `team` executes under *s (the same worksharing routines, sec. 1 and
+ * sec. 2).  Same errors as omprt_for_static_bounds. */
 omprt_status omprt_sched_count(const omprt_sched *s, int32_t team,
                                int32_t thread, int64_t *n_chunks,
                                int64_t *n_iters);
@@ -166,7 +180,9 @@ omprt_status omprt_sched_count(const omprt_sched *s, int32_t team,
  * to count[i].  d_owner and d_count have s->n entries; the caller zeroes
  * d_count first (a correct map leaves every count at 1).  num_teams and
  * threads_per_team must be given (no runtime choice).  Verification
- * kernel for the schedule semantics.
+ * kernel for the schedule semantics of the worksharing routines (sec. 1,
+ * sec. 2) under the team-to-thread-block mapping (sec. 3.1); the count uses
+ * the device atomic add (sec. 3.1, "Atomic Operations").
  */
 omprt_status omprt_static_map(const omprt_sched *s, int32_t *d_owner,
                               uint32_t *d_count, void *hip_stream);
@@ -187,7 +203,22 @@ omprt_status omprt_static_map(const omprt_sched *s, int32_t *d_owner,
  * schedule(static) run instead; sum, max and min).  The cross-team
  * combine is done by the last team to finish, found with a wrap-around
  * atomic increment that leaves its counter at 0.
+ * Defining passages: the region is a teams distribute parallel for with a
+ * reduction clause, whose iterations the runtime divides (sec. 1, sec. 2);
+ * one team is one thread block and its tree lives in team-shared memory,
+ * which is uninitialised until written (sec. 3.1, "Global Shared
+ * Variables", and the shared variables of the listing of the flush entry);
+ * the last team is elected with the wrap-around increment inc,
+ * { v = x; x = x >= e ? 0 : x + 1 } with e = T - 1 (sec. 3.1, "Atomic
+ * Operations"; its AMD builtin in the declare-variant listing of sec. 3.2).
+ * The flush of that listing is a device-wide fence; this library makes the
+ * partials visible through tagged agent-scope atomic slot words instead, so
+ * no team pays for a fence.
  * d_in needs only element alignment.  cfg may be NULL.
+ * Errors: UNSUPPORTED for a dtype or op outside the enums or an op the
+ * dtype does not define; INVALID for n outside 0..2^50, NULL x, NULL d_in
+ * with n > 0, misaligned pointers, or cfg fields out of range; NOMEM when
+ * the workspace cannot grow; DEVICE for a failed launch.
  */
 omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
                           int32_t op, void *d_x, const omprt_config *cfg,
@@ -391,6 +422,16 @@ omprt_status omprt_reduce_array_plan(int64_t rows, int64_t m, int32_t dtype,
  * outputs.  cfg's threads_per_team / unroll / vec_bytes select the tile
  * kernel; num_teams the persistent grid size (0 = one full wave of the
  * device).
+ * Defining passages: each segment is one reduction region with omprt_reduce's
+ * semantics; the tiles of a segment play its teams: each reduces its part
+ * through the team-shared tree and the last tile, elected by the wrap-around
+ * inc with e = tiles - 1, combines (sec. 3.1, "Global Shared Variables" and
+ * "Atomic Operations").  Running many regions in one persistent launch is
+ * this library's extension; the paper has no batched form.
+ * Errors: as omprt_reduce per segment (with the segment index in the
+ * message); INVALID for count < 0, NULL h_segs with count > 0, or a plan
+ * built while the stream is being captured (make the call once before
+ * capturing); NOMEM for the plan's tables.
  */
 omprt_status omprt_reduce_batched(const omprt_segment *h_segs, int32_t count,
                                   const omprt_config *cfg, void *hip_stream);
@@ -409,6 +450,11 @@ omprt_status omprt_reduce_each(const omprt_segment *h_segs, int32_t count,
  * On exit *d_sum <- *d_sum + sum (compensated fp32 as in omprt_reduce).
  * s->num_teams / threads_per_team of 0 let the runtime pick; dist_chunk and
  * chunk are honoured exactly.  x and y must not overlap.
+ * Defining passages: a worksharing loop whose iterations the runtime
+ * divides (sec. 1, sec. 2), with the schedule of omprt_for_static_bounds and
+ * the reduction protocol of omprt_reduce (sec. 3.1).
+ * Errors: INVALID for a bad schedule, NULL or misaligned pointers,
+ * overlapping x and y, or more than 65535 teams.
  */
 omprt_status omprt_axpy_sum(float a, const float *d_x, float *d_y,
                             float *d_sum, const omprt_sched *s,
@@ -496,11 +542,22 @@ omprt_status omprt_axpy_sum_queue(float a, const float *d_x, float *d_y,
                                   int32_t kind, void *hip_stream);
 
 /*
- * An empty target region: one launch of s->num_teams teams in which every
- * thread computes its static-schedule bounds over s->n iterations and runs
- * an empty body, then the team barrier.  For launch-latency measurement.
+ * An empty target region with a trivial loop body: one launch of
+ * s->num_teams teams over s->n iterations under s's static schedule whose
+ * body only counts, reduction(+: iters) with one count per iteration.
+ * Every thread works out its chunks, the counts go through the team tree
+ * and the cross-team step like any reduction, and the last team checks
+ * that the region ran exactly s->n iterations (the worksharing routines of
+ * sec. 1 / sec. 2.1 plus the team-shared tree and the wrap-increment
+ * election of sec. 3.1, with nothing else in the launch).  For launch
+ * latency measurement and as a device-side check of the schedule
+ * arithmetic.  d_iters (int64, may be NULL) receives *d_iters += the count.
+ * A thread whose chunks are inconsistent, or a total other than s->n, sets
+ * status bit 16 (omprt_workspace_status).  Errors: as check of *s, plus
+ * INVALID for num_teams above 65535 or a misaligned d_iters.
  */
-omprt_status omprt_empty_region(const omprt_sched *s, void *hip_stream);
+omprt_status omprt_empty_region(const omprt_sched *s, int64_t *d_iters,
+                                void *hip_stream);
 
 /* ----------------------------------------------------------------------- */
 /* Device atomics                                                          */
@@ -623,7 +680,8 @@ omprt_status omprt_workspace_reset(void *hip_stream);
  * happens if a participant was lost, e.g. an aborted launch); bit 2 = an
  * omprt_atomic_apply operation had an out-of-range index; bit 4 = an
  * omprt_histogram key was outside [0, bins); bit 8 = a team-shared
- * allocation found no room (its launch did nothing).  The bits stay set
+ * allocation found no room (its launch did nothing); bit 16 = an
+ * omprt_empty_region launch found its schedule inconsistent.  The bits stay set
  * until omprt_workspace_reset (which also re-zeroes the array-reduction
  * counters).
  */

@@ -116,9 +116,11 @@ def static_map(n, teams, threads, dist_chunk, chunk, owner, count, stream=None):
           "static_map")
 
 
-def empty_region(n, teams, threads, dist_chunk=0, chunk=0, stream=None):
+def empty_region(n, teams, threads, dist_chunk=0, chunk=0, iters=None, stream=None):
+    """Empty target region; iters (int64 device tensor or None) gets += the iteration count."""
     s = _sched(n, teams, threads, dist_chunk, chunk)
-    check(load().omprt_empty_region(ctypes.byref(s), _stream(stream)), "empty_region")
+    check(load().omprt_empty_region(ctypes.byref(s), _ptr(iters), _stream(stream)),
+          "empty_region")
 
 
 # ---------------------------------------------------------------- reductions
@@ -373,7 +375,9 @@ def workspace_reset(stream=None):
 
 
 def workspace_status(stream=None) -> int:
-    """Synchronise the stream; 0 if every cross-team wait completed, 1 otherwise."""
+    """Synchronise the stream; 0 when healthy, else the status bits (1 a cross-team wait
+    expired, 2 an atomic index out of range, 4 a histogram key out of range, 8 a
+    team-shared allocation found no room, 16 an empty region's schedule inconsistent)."""
     v = ctypes.c_int32()
     check(load().omprt_workspace_status(_stream(stream), ctypes.byref(v)), "workspace_status")
     return v.value

@@ -5,6 +5,7 @@ fallback implementation of any entry point.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -71,7 +72,7 @@ SIGNATURES = {
     "omprt_reduce_each": (_i32, [ctypes.POINTER(Segment), _i32, _C, _p]),
     "omprt_axpy_sum": (_i32, [_f32, _p, _p, _p, _S, _C, _p]),
     "omprt_region_axpy_sum": (_i32, [_f32, _p, _p, _p, _S, _i64, _i32, _C, _p]),
-    "omprt_empty_region": (_i32, [_S, _p]),
+    "omprt_empty_region": (_i32, [_S, _p, _p]),
     "omprt_atomic_apply": (_i32, [_i32, _p, _i64, _p, _p, _p, _p, _i64, _p]),
     "omprt_queue_chunk": (_i32, [_i32, _i64, _i32, _i64, _i64, _p, _p]),
     "omprt_queue_map": (_i32, [_S, _i32, _i32, _p, _p, _p, _p]),
@@ -110,7 +111,18 @@ def load() -> ctypes.CDLL:
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    # explicit teardown while the HIP runtime is still up: the library frees its
+    # device memory here, never from static destructors at process exit
+    atexit.register(_finalize_at_exit)
     return lib
+
+
+def _finalize_at_exit() -> None:
+    if _lib is not None:
+        try:
+            _lib.omprt_finalize()
+        except Exception:   # noqa: BLE001 -- nothing can be reported at exit
+            pass
 
 
 class OmprtError(RuntimeError):

@@ -95,10 +95,7 @@ static omprt_status array_ws_get(hipStream_t stream, int64_t counters, int64_t w
         void* p = nullptr;
         if (hipMalloc(&p, bytes) != hipSuccess)
             return fail(OMPRT_ERR_NOMEM, "array workspace allocation of %zu bytes failed", bytes);
-        if (ws.base) {
-            OMPRT_HIP(hipStreamSynchronize(stream));
-            OMPRT_HIP(hipFree(ws.base));
-        }
+        retire_device_memory(dev, ws.base);   // a captured graph may still name it
         ws.base = p;
         ws.counters = nc;
         ws.words = nw;

@@ -169,10 +169,15 @@ struct Plan {
     hipGraphExec_t exec = nullptr;
     int32_t ntiles = 0;
     uint32_t* status = nullptr;
-    ~Plan() {
+    // Explicit, never from a destructor: a plan still alive when the process
+    // exits is left to the driver (no HIP call runs from static destruction).
+    void release() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (dmem) (void)hipFree(dmem);
+        exec = nullptr;
+        graph = nullptr;
+        dmem = nullptr;
     }
 };
 
@@ -180,6 +185,9 @@ static std::mutex g_bmu;
 // one cached plan per (device, stream): a repeat call with the same segment
 // list and configuration replays its graph
 static std::map<std::pair<int, hipStream_t>, std::unique_ptr<Plan>> g_plans;
+// superseded plans: a graph the caller captured around an earlier call may
+// still replay their launch, so they live until omprt_finalize
+static std::vector<std::unique_ptr<Plan>> g_retired_plans;
 static std::map<int, hipStream_t> g_capture_stream;
 
 static bool same_plan(const Plan& p, const omprt_segment* s, int32_t count,
@@ -286,7 +294,17 @@ static omprt_status build_plan(Plan& p, hipStream_t user_stream) {
 
 void batched_finalize() {
     std::lock_guard<std::mutex> lk(g_bmu);
+    for (auto& kv : g_plans)
+        if (kv.second) {
+            (void)hipSetDevice(kv.second->device);
+            kv.second->release();
+        }
+    for (auto& p : g_retired_plans) {
+        (void)hipSetDevice(p->device);
+        p->release();
+    }
     g_plans.clear();
+    g_retired_plans.clear();
     for (auto& kv : g_capture_stream)
         if (kv.second) (void)hipStreamDestroy(kv.second);
     g_capture_stream.clear();
@@ -314,20 +332,20 @@ extern "C" omprt_status omprt_reduce_batched(const omprt_segment* h_segs, int32_
     std::lock_guard<std::mutex> lk(g_bmu);
     std::unique_ptr<Plan>& slot = g_plans[{dev, stream}];
     if (!slot || !same_plan(*slot, h_segs, count, c)) {
-        if (slot) {
-            OMPRT_HIP(hipStreamSynchronize(stream));   // previous replays may still run
-            slot.reset();
-        }
         hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
         OMPRT_HIP(hipStreamIsCapturing(stream, &cst));
         if (cst != hipStreamCaptureStatusNone)
             return fail(OMPRT_ERR_INVALID, "omprt_reduce_batched builds its plan outside capture");
+        if (slot) g_retired_plans.push_back(std::move(slot));   // replays may still run
         std::unique_ptr<Plan> p(new Plan());
         p->device = dev;
         p->stream = stream;
         p->segs.assign(h_segs, h_segs + count);
         p->cfg = c;
-        if (omprt_status st = build_plan(*p, stream)) return st;
+        if (omprt_status st = build_plan(*p, stream)) {
+            p->release();
+            return st;
+        }
         slot = std::move(p);
     }
     if (slot->ntiles == 0) return OMPRT_OK;

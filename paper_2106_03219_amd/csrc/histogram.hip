@@ -223,10 +223,7 @@ static omprt_status pool_get(hipStream_t stream, uint64_t bytes, void** out) {
         void* q = nullptr;
         if (hipMalloc(&q, bytes) != hipSuccess)
             return fail(OMPRT_ERR_NOMEM, "histogram pool of %llu bytes", (unsigned long long)bytes);
-        if (p.ptr) {
-            OMPRT_HIP(hipStreamSynchronize(stream));
-            OMPRT_HIP(hipFree(p.ptr));
-        }
+        retire_device_memory(dev, p.ptr);   // a captured graph may still name it
         p.ptr = q;
         p.bytes = bytes;
     }

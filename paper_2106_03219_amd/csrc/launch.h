@@ -41,8 +41,10 @@ hipError_t launch_axpy_sum(float a, const float* x, float* y, float* sum, int64_
                            int teams, int threads, int64_t dist_chunk, int64_t chunk,
                            const CrossTeamArgs& ct, hipStream_t stream);
 
-// Empty target region over n iterations.
+// Empty target region over n iterations with reduction(+: iters) of one
+// count per iteration (iters may be NULL); inconsistencies set status bit 16.
 hipError_t launch_empty_region(int64_t n, int teams, int threads, int64_t dist_chunk,
-                               int64_t chunk, int32_t* flag, hipStream_t stream);
+                               int64_t chunk, int64_t* iters, const CrossTeamArgs& ct,
+                               hipStream_t stream);
 
 }  // namespace omprt

@@ -126,18 +126,25 @@ static omprt_status mlp_scratch(hipStream_t s, int64_t floats, float** out) {
         OMPRT_HIP(hipStreamIsCapturing(s, &cs));
         if (cs != hipStreamCaptureStatusNone)
             return fail(OMPRT_ERR_INVALID, "MLP scratch must grow outside stream capture");
-        if (m.base) {
-            OMPRT_HIP(hipStreamSynchronize(s));
-            OMPRT_HIP(hipFree(m.base));
-            m.base = nullptr;
-            m.floats = 0;
-        }
-        if (hipMalloc(&m.base, sizeof(float) * (size_t)floats) != hipSuccess)
+        float* q = nullptr;
+        if (hipMalloc(&q, sizeof(float) * (size_t)floats) != hipSuccess)
             return fail(OMPRT_ERR_NOMEM, "MLP scratch allocation failed");
+        retire_device_memory(dev, m.base);   // a captured graph may still name it
+        m.base = q;
         m.floats = floats;
     }
     *out = m.base;
     return OMPRT_OK;
+}
+
+void mlp_finalize() {
+    std::lock_guard<std::mutex> lk(g_mmu);
+    for (auto& kv : g_mscr) {
+        if (!kv.second.base) continue;
+        (void)hipSetDevice(kv.first.first);
+        (void)hipFree(kv.second.base);
+    }
+    g_mscr.clear();
 }
 
 static omprt_status check_dims(const omprt_mlp_dims* d) {

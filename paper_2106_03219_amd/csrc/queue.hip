@@ -247,14 +247,10 @@ static omprt_status guided_table(hipStream_t stream, int64_t m, int64_t P, int64
                     "stream is being captured and the guided table for this block size is not "
                     "built yet: make the same call once before capturing");
     if (g_tables.size() >= kMaxTables) {
-        // many distinct block sizes: drop them all once the device is idle
-        OMPRT_HIP(hipDeviceSynchronize());
-        for (auto& kv : g_tables) {
-            (void)hipSetDevice(kv.first.dev);
-            (void)hipFree(kv.second.ptr);
-        }
+        // many distinct block sizes: start a new cache (captured graphs may still name
+        // the old tables, so they wait for omprt_finalize)
+        for (auto& kv : g_tables) retire_device_memory(kv.first.dev, kv.second.ptr);
         g_tables.clear();
-        OMPRT_HIP(hipSetDevice(dev));
     }
     const std::vector<int64_t> b = guided_bounds(m, P, cmin);
     DevTable t;

@@ -137,30 +137,64 @@ hipError_t launch_reduce(int dtype, int op, int vec_bytes, int unroll, const voi
 
 // ---------------------------------------------------------------- empty region
 
-// Every thread computes the bounds of its first chunk of the static schedule
-// and runs an empty body; then the team barrier ends the region.  The flag
-// store can only happen for an inconsistent schedule, which keeps the bounds
-// computation from being optimised away.
+// A target region whose loop body does nothing but reduction(+: iters) with
+// one count per iteration, so the launch carries the whole region protocol:
+// every thread works out its static-schedule chunks (in closed form: the
+// team's full distribute blocks share one per-thread count, only its last
+// block can be partial) and checks its first and last chunk for consistency;
+// the counts meet in the wave / LDS tree and the cross-team step, and the
+// last team compares the total with n.  A thread with an inconsistent chunk,
+// or a total other than n, sets status bit 16; iters (may be NULL) receives
+// the total.
 __global__ __launch_bounds__(1024) void empty_region_kernel(int64_t n, int P, int64_t dc,
-                                                            int64_t c, int32_t* flag) {
+                                                            int64_t c, int64_t* iters,
+                                                            CrossTeam ct) {
+    using R = Red<DT_I64, OP_SUM>;
+    __shared__ uint64_t lds_slots[kMaxWaves];
+    __shared__ int s_last;
     const int64_t T = gridDim.x, k = blockIdx.x;
     const int t = threadIdx.x;
-    if (t < P && team_nblocks(n, T, dc, k) > 0) {
-        const Range blk = team_block(n, T, dc, k, 0);
-        const int64_t m = blk.hi - blk.lo;
-        if (thread_nchunks(m, P, c, t) > 0) {
-            const Range ch = thread_chunk(blk.lo, m, P, c, t, 0);
-            if (ch.lo >= ch.hi) flag[0] = 1;
+    const uint32_t epoch = T > 1 ? read_epoch(ct.epoch) : 0u;
+    uint64_t cnt = 0;
+    bool bad = false;
+    const int64_t nb = t < P ? team_nblocks(n, T, dc, k) : 0;
+    if (nb > 0) {
+        const Range first = team_block(n, T, dc, k, 0);
+        const Range last = team_block(n, T, dc, k, nb - 1);
+        const int64_t m0 = first.hi - first.lo, m1 = last.hi - last.lo;
+        cnt = (uint64_t)(thread_niters(m0, P, c, t) * (nb - 1) + thread_niters(m1, P, c, t));
+        const int64_t nc = thread_nchunks(m0, P, c, t);
+        if (nc > 0) {
+            const Range a = thread_chunk(first.lo, m0, P, c, t, 0);
+            const Range z = thread_chunk(first.lo, m0, P, c, t, nc - 1);
+            bad = !(first.lo <= a.lo && a.lo < a.hi && a.hi <= z.hi && z.lo < z.hi &&
+                    z.hi <= first.hi && (nc == 1 || a.hi <= z.lo));
         }
+        if (nb > 1 && !(first.hi <= last.lo && last.hi <= n)) bad = true;
     }
-    __syncthreads();
+    if (bad) __hip_atomic_fetch_or(ct.status, 16u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t total = team_reduce<R>(cnt, lds_slots);
+    if (T > 1) {
+        const uint32_t tag = launch_tag(epoch);
+        if (!publish_and_elect(total, ct.slots + (size_t)blockIdx.x * kSlotWords, ct.counter,
+                               (uint32_t)(T - 1), tag, &s_last))
+            return;
+        total = combine_slots<R>(ct.slots, T, tag, ct.status, lds_slots);
+    }
+    if (t == 0) {
+        if (total != (uint64_t)n)
+            __hip_atomic_fetch_or(ct.status, 16u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (iters) iters[0] = R::finish(total, iters[0]);
+        if (T > 1) advance_epoch(ct.epoch, epoch);
+    }
 }
 
 hipError_t launch_empty_region(int64_t n, int teams, int threads, int64_t dist_chunk,
-                               int64_t chunk, int32_t* flag, hipStream_t stream) {
+                               int64_t chunk, int64_t* iters, const CrossTeamArgs& ct,
+                               hipStream_t stream) {
     const int block = (threads + kWave - 1) / kWave * kWave;
     hipLaunchKernelGGL(empty_region_kernel, dim3(teams), dim3(block), 0, stream, n, threads,
-                       dist_chunk, chunk, flag);
+                       dist_chunk, chunk, iters, to_device_ct(ct));
     return hipGetLastError();
 }
 

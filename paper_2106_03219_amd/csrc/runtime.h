@@ -28,19 +28,22 @@ int dtype_bytes(int dtype);         // storage bytes of an input element
 int out_bytes(int dtype, int op);   // bytes of x
 
 // Per (device, stream) workspace of the plain kernels: a 256-byte header
-// (election counter, empty-region flag, launch epoch, poll-timeout status;
-// zeroed once at allocation, self-maintaining afterwards) followed by the
-// tagged cross-team slots.
+// (election counter, launch epoch, status bits; zeroed once at allocation,
+// self-maintaining afterwards) followed by the tagged cross-team slots.
 struct Workspace {
     void* base = nullptr;
     int32_t capacity = 0;   // slots
     uint32_t* counter() const { return static_cast<uint32_t*>(base); }
-    int32_t* flag() const { return static_cast<int32_t*>(base) + 16; }
     uint32_t* epoch() const { return static_cast<uint32_t*>(base) + 32; }
     uint32_t* status() const { return static_cast<uint32_t*>(base) + 48; }
     void* slots() const { return static_cast<char*>(base) + 256; }
     CrossTeamArgs cross() const { return CrossTeamArgs{slots(), counter(), epoch(), status()}; }
 };
+
+// Device memory a caller's captured graph may still name is never freed while
+// the library is in use: a buffer that a larger one supersedes waits on this
+// list (no synchronisation needed) until omprt_finalize frees it.
+void retire_device_memory(int dev, void* p);
 
 // Workspace of `stream` with room for `teams` slots, allocated or grown
 // here (never while the stream is being captured).
@@ -65,6 +68,9 @@ int device_cus();
 // Batched plans (batched.hip): free everything; status word of a stream's plan.
 void batched_finalize();
 uint32_t* batched_status_word(int dev, hipStream_t stream);
+
+// MLP kernels (mlp.hip): free the scratch buffers.
+void mlp_finalize();
 
 // Histograms (histogram.hip): free the pools.
 void histogram_finalize();

@@ -12,6 +12,7 @@
 #include <string>
 #include <tuple>
 #include <utility>
+#include <vector>
 
 #include "launch.h"
 #include "runtime.h"
@@ -55,6 +56,24 @@ static std::mutex g_mu;
 static std::map<std::pair<int, hipStream_t>, Workspace> g_ws;   // node addresses are stable
 static std::atomic<uint64_t> g_ws_generation{1};                // bumped when workspaces are freed
 
+static std::mutex g_retire_mu;
+static std::vector<std::pair<int, void*>> g_retired;
+
+void retire_device_memory(int dev, void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_retire_mu);
+    g_retired.emplace_back(dev, p);
+}
+
+static void free_retired() {
+    std::lock_guard<std::mutex> lk(g_retire_mu);
+    for (auto& r : g_retired) {
+        (void)hipSetDevice(r.first);
+        (void)hipFree(r.second);
+    }
+    g_retired.clear();
+}
+
 // Last workspace this host thread used: a repeat call on the same stream
 // skips the lock and the map (a stream is never shared between threads).
 struct WsMemo {
@@ -88,10 +107,8 @@ omprt_status workspace_get(hipStream_t stream, int32_t teams, Workspace** out) {
         void* p = nullptr;
         if (hipMalloc(&p, 256 + (size_t)cap * kSlotBytes) != hipSuccess)
             return fail(OMPRT_ERR_NOMEM, "workspace allocation of %d slots failed", cap);
-        if (ws.base) {
-            OMPRT_HIP(hipStreamSynchronize(stream));   // earlier launches may still read it
-            OMPRT_HIP(hipFree(ws.base));
-        }
+        // earlier launches, and graphs a caller captured, may still use the old one
+        retire_device_memory(dev, ws.base);
         ws.base = p;
         ws.capacity = cap;
         // header and slots, once: tags are odd, so zeroed slots never match
@@ -276,17 +293,7 @@ extern "C" omprt_status omprt_sched_count(const omprt_sched* s, int32_t team, in
     if (L.nb > 0) {
         const int64_t full_blocks = L.last_partial ? L.nb - 1 : L.nb;
         chunks = full_blocks * L.f + (L.last_partial ? L.g : 0);
-        // iterations: every block's share, summed in closed form per block kind
-        auto share = [&](int64_t m) -> int64_t {
-            if (s->chunk == 0) {
-                const Range r = bal_share(m, P, thread);
-                return r.hi - r.lo;
-            }
-            const int64_t nc = thread_nchunks(m, P, s->chunk, thread);
-            if (nc == 0) return 0;
-            const Range lastc = thread_chunk(0, m, P, s->chunk, thread, nc - 1);
-            return (nc - 1) * s->chunk + (lastc.hi - lastc.lo);
-        };
+        auto share = [&](int64_t m) -> int64_t { return thread_niters(m, P, s->chunk, thread); };
         if (s->dist_chunk == 0) {
             const Range b = team_block(s->n, s->num_teams, 0, team, 0);
             iters = share(b.hi - b.lo);
@@ -414,13 +421,18 @@ extern "C" omprt_status omprt_axpy_sum(float a, const float* d_x, float* d_y, fl
     return OMPRT_OK;
 }
 
-extern "C" omprt_status omprt_empty_region(const omprt_sched* s, void* hip_stream) {
+extern "C" omprt_status omprt_empty_region(const omprt_sched* s, int64_t* d_iters,
+                                           void* hip_stream) {
     if (omprt_status st = check_sched(s, false)) return st;
+    if (s->num_teams > 65535)
+        return fail(OMPRT_ERR_INVALID, "num_teams %d above 65535 (cross-team slot limit)",
+                    s->num_teams);
+    if (omprt_status st = check_ptr_align(d_iters, 8, "iters")) return st;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     Workspace* ws = nullptr;
-    if (omprt_status st = workspace_get(stream, 1, &ws)) return st;
+    if (omprt_status st = workspace_get(stream, s->num_teams, &ws)) return st;
     const hipError_t e = launch_empty_region(s->n, s->num_teams, s->threads_per_team,
-                                             s->dist_chunk, s->chunk, ws->flag(), stream);
+                                             s->dist_chunk, s->chunk, d_iters, ws->cross(), stream);
     if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "empty launch: %s", hipGetErrorString(e));
     return OMPRT_OK;
 }
@@ -524,6 +536,7 @@ extern "C" omprt_status omprt_finalize(void) {
     array_finalize();
     queue_finalize();
     histogram_finalize();
+    mlp_finalize();
     udr_finalize();
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_ws) {
@@ -533,6 +546,7 @@ extern "C" omprt_status omprt_finalize(void) {
     }
     g_ws.clear();
     g_ws_generation.fetch_add(1, std::memory_order_acq_rel);
+    free_retired();
     OMPRT_HIP(hipSetDevice(dev));
     return OMPRT_OK;
 }

@@ -72,4 +72,18 @@ OMPRT_HD Range thread_chunk(int64_t a, int64_t m, int64_t P, int64_t c, int64_t 
     return Range{a + lo, a + hi};
 }
 
+// Iterations thread t executes inside a block of m iterations (the sizes of
+// its chunks summed in closed form: all but the last have c iterations).
+OMPRT_HD int64_t thread_niters(int64_t m, int64_t P, int64_t c, int64_t t) {
+    if (m <= 0) return 0;
+    if (c == 0) {
+        const Range r = bal_share(m, P, t);
+        return r.hi - r.lo;
+    }
+    const int64_t nc = thread_nchunks(m, P, c, t);
+    if (nc == 0) return 0;
+    const Range last = thread_chunk(0, m, P, c, t, nc - 1);
+    return (nc - 1) * c + (last.hi - last.lo);
+}
+
 }  // namespace omprt

@@ -8,13 +8,20 @@ so an interrupted run resumes where it stopped.  The autotuner's choice for
 an instance is the argmin class; it labels the network's training data and
 judges its regret.
 
-Class grid (32 classes, shared with the model file's class table):
-threads {128, 256, 512, 1024} x teams per CU {1, 2, 4, 8} x unroll {2, 4},
-16-byte loads.  Teams for a call = min(teams_per_cu * CUs,
-ceil(n * bytes_per_iter / (threads * 16))), at least 1 -- the same rule the
-runtime applies when the model picks a class.  For the AXPY body only teams
-and threads matter, so unroll-2 and unroll-4 classes of the same
-(teams, threads) share one timing.
+Class grid (64 classes, shared with the model file's class table):
+threads {128, 256, 512, 1024} x teams per CU {1, 2, 4, 8} x bytes per lane
+per load {8, 16} x loads in flight {2, 4}.  Teams for a call =
+min(teams_per_cu * CUs, ceil(n * bytes_per_iter / (threads * vec))), at
+least 1 -- the same rule the runtime applies when the model picks a class.
+For the AXPY body only teams and threads matter (its kernel fixes its own
+loads), so classes that give the same (teams, threads) share one timing.
+
+Every record also keeps the result each distinct configuration computed
+(plain reductions from the op's identity; AXPY sums from a pristine y and a
+zero sum), so the timed runs can be checked against an independent
+reference afterwards: the instances are prefixes of a few shared buffers,
+whose host copies a checker folds once per (dtype, op) at every prefix
+length.
 
     python -m paper_2106_03219_amd.tune --out DB.jsonl --count 20000 --seed 7
 """
@@ -29,9 +36,10 @@ import time
 
 THREADS = (128, 256, 512, 1024)
 TEAMS_PER_CU = (1, 2, 4, 8)
+VECS = (8, 16)
 UNROLLS = (2, 4)
-VEC = 16
-CLASSES = [(tpc, th, VEC, un) for th in THREADS for tpc in TEAMS_PER_CU for un in UNROLLS]
+CLASSES = [(tpc, th, vec, un) for th in THREADS for tpc in TEAMS_PER_CU for vec in VECS
+           for un in UNROLLS]
 
 ELEM_BYTES = {0: 4, 1: 8, 2: 4, 3: 8, 4: 2}
 AXPY_A = 0.7
@@ -49,18 +57,22 @@ def class_config(cls, n, bytes_per_iter, cus):
             "unroll": unroll}
 
 
-class Buffers:
-    """One max-size device buffer per dtype; instances use prefix views."""
+BUFFER_SEED = 1234
 
-    def __init__(self, max_n, seed=1234):
+
+class Buffers:
+    """One max-size device buffer per dtype (seed BUFFER_SEED + dtype code) and the
+    AXPY y (seed BUFFER_SEED + 10, kept pristine in y0); instances use prefix views."""
+
+    def __init__(self, max_n, seed=BUFFER_SEED):
         import synth
         import torch
         self.torch = torch
         self.t = {}
         for dt in (synth.I32, synth.I64, synth.F32, synth.BF16):
             self.t[dt] = synth.device(dt, max_n, seed + dt)
-        self.y = synth.device(synth.F32, max_n, seed + 10)
-        self.x_out = {dt: torch.zeros(1, dtype=torch.float64, device="cuda") for dt in self.t}
+        self.y0 = synth.device(synth.F32, max_n, seed + 10)
+        self.y = self.y0.clone()
 
     def x_for(self, dtype, op):
         torch = self.torch
@@ -82,60 +94,67 @@ def time_call(fn, reps, torch):
     return min(a.elapsed_time(b) for a, b in evs) * 1e3   # microseconds
 
 
+def _value(x):
+    return float(x.float().item()) if x.dtype.is_floating_point else int(x.item())
+
+
 def tune_instance(om, bufs, inst, cus, torch):
+    """Times of every class (in CLASSES order) and of the heuristic for one instance,
+    and the distinct configurations' results: a list of [teams, threads, vec, unroll,
+    value] (AXPY: [teams, threads, 0, 0, sum]); the heuristic's is the last."""
     n, dt, op, body, chunk = inst["n"], inst["dtype"], inst["op"], inst["body"], inst["chunk"]
     bpi = 12 if body else ELEM_BYTES[dt]
     big = n * bpi > (64 << 20)
     reps = 3 if big else 5
     times = []
     cache = {}
+    results = []
     if body:
         x = bufs.t[2][:n]
         y = bufs.y[:n]
         s = torch.zeros(1, dtype=torch.float32, device="cuda")
         c = 0 if chunk < 0 else chunk
+
+        def axpy(teams, threads, config=None):
+            return lambda: om.axpy_sum(AXPY_A, x, y, s, teams, threads, 0, c, config=config)
+
+        def result(run):
+            y.copy_(bufs.y0[:n])
+            s.zero_()
+            run()
+            return _value(s)
         for cls in CLASSES:
             cfg = class_config(cls, n, bpi, cus)
             key = (cfg["teams"], cfg["threads"])
             if key not in cache:
-                cache[key] = time_call(lambda: om.axpy_sum(AXPY_A, x, y, s, cfg["teams"], cfg["threads"],
-                                                           0, c), reps, torch)
+                cache[key] = time_call(axpy(*key), reps, torch)
+                results.append([key[0], key[1], 0, 0, result(axpy(*key))])
             times.append(cache[key])
-        hcfg, _ = om.resolve_config(n, dt, op, 1, chunk, {"flags": om.CFG_NO_MODEL})
-        t_heur = time_call(lambda: om.axpy_sum(AXPY_A, x, y, s, 0, 0, 0, c,
-                                               config={"flags": om.CFG_NO_MODEL}), reps, torch)
+        heur = axpy(0, 0, {"flags": om.CFG_NO_MODEL})
+        t_heur = time_call(heur, reps, torch)
+        results.append([0, 0, 0, 0, result(heur)])
+        y.copy_(bufs.y0[:n])
     else:
         inp = bufs.t[dt][:n]
         xo = bufs.x_for(dt, op)
-        cfgs = {}
+        cfgs = []
         for cls in CLASSES:
             cfg = class_config(cls, n, bpi, cus)
             key = tuple(cfg.values())
             if key not in cache:
                 cache[key] = time_call(lambda: om.reduce(inp, op, xo, config=cfg), reps, torch)
-                cfgs[key] = cfg
+                cfgs.append(cfg)
             times.append(cache[key])
         hcfg, _ = om.resolve_config(n, dt, op, 0, -1, {"flags": om.CFG_NO_MODEL})
         t_heur = time_call(lambda: om.reduce(inp, op, xo, config=hcfg), reps, torch)
-        check_consistent(om, inp, dt, op, list(cfgs.values()) + [hcfg], torch)
-    return times, t_heur
-
-
-def check_consistent(om, inp, dt, op, cfgs, torch):
-    """Every timed configuration must produce the same reduction from the identity:
-    bit-identical for integers and max/min, within 2e-6 relative for compensated
-    floating sums (each is within 1e-6 of the exact sum).  Raises otherwise."""
-    one = [bufs_identity(torch, dt, op) for _ in cfgs]
-    for cfg, x in zip(cfgs, one):
-        om.reduce(inp, op, x, config=cfg)
-    torch.cuda.synchronize()
-    vals = [float(x.float().item()) if x.dtype == torch.bfloat16 else x.item() for x in one]
-    if op == 0 and dt in (2, 3, 4):
-        ref = max(abs(v) for v in vals)
-        if ref > 0 and (max(vals) - min(vals)) > 2e-6 * ref:
-            raise RuntimeError(f"configurations disagree on a floating sum: {vals}")
-    elif len(set(vals)) != 1:
-        raise RuntimeError(f"configurations disagree: {vals}")
+        cfgs.append(hcfg)
+        outs = [bufs_identity(torch, dt, op) for _ in cfgs]
+        for cfg, xv in zip(cfgs, outs):
+            om.reduce(inp, op, xv, config=cfg)
+        torch.cuda.synchronize()
+        results = [[cfg["teams"], cfg["threads"], cfg["vec"], cfg["unroll"], _value(xv)]
+                   for cfg, xv in zip(cfgs, outs)]
+    return times, t_heur, results
 
 
 def bufs_identity(torch, dt, op):
@@ -186,9 +205,11 @@ def main(argv=None):
             rec = {"id": i, "n": int(inst["n"][i]), "dtype": int(inst["dtype"][i]),
                    "op": int(inst["op"][i]), "body": int(inst["body"][i]),
                    "chunk": int(inst["chunk"][i])}
-            times, th = tune_instance(om, bufs, rec, cus, torch)
+            times, th, results = tune_instance(om, bufs, rec, cus, torch)
             rec["times_us"] = [round(t, 3) for t in times]
             rec["heuristic_us"] = round(th, 3)
+            rec["results"] = results
+            rec["buffer_n"] = max_n
             fh.write(json.dumps(rec) + "\n")
             if k % 500 == 0:
                 fh.flush()

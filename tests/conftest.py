@@ -1,3 +1,5 @@
+import json
+import math
 import os
 import sys
 
@@ -22,3 +24,27 @@ def gpu_lib():
     import paper_2106_03219_amd as omprt
     omprt.load()          # raises if libomprt.so is missing
     return omprt
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Per-result error report of the floating sums the GPU tests checked: the worst
+    relative error against the oracle per test, with its kappa."""
+    mod = sys.modules.get("gpu_util")
+    errs = getattr(mod, "ERRORS", None) if mod else None
+    if not errs:
+        return
+    worst = {}
+    for e in errs:
+        w = worst.get(e["test"])
+        if w is None or e["rel"] > w["rel"]:
+            worst[e["test"]] = e
+    tr = terminalreporter
+    tr.write_sep("-", f"floating sums vs the FP64 oracle: {len(errs)} results, worst per test")
+    for t, e in sorted(worst.items(), key=lambda kv: -kv[1]["rel"]):
+        k = "inf" if math.isinf(e["kappa"]) else f"{e['kappa']:.3g}"
+        tr.write_line(f"rel {e['rel']:.3e}  kappa {k:>9}  {e['dtype']:>4}  {t}  {e['what']}")
+    path = os.environ.get("OMPRT_ERROR_REPORT")
+    if path:
+        with open(path, "w") as fh:
+            json.dump([{**e, "kappa": None if math.isinf(e["kappa"]) else e["kappa"]}
+                       for e in errs], fh)

@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import check_value, identity, oracle_value, to_device, x_tensor, x_value
+from gpu_util import check_axpy, check_value, identity, oracle_value, to_device, x_tensor, x_value
 
 pytestmark = pytest.mark.gpu
 
@@ -48,8 +48,7 @@ def test_model_picked_launches_match_oracle(model):
             om.axpy_sum(0.7, xd, yd, s, 0, 0, 0, max(ch, 0))
             torch.cuda.synchronize()
             y_ref, s_ref = oracle.axpy_sum(0.7, x, y)
-            assert np.array_equal(yd.cpu().numpy().view(np.uint32), y_ref.view(np.uint32))
-            assert abs(s.item() - s_ref) <= 1e-6 * abs(s_ref)
+            check_axpy(yd.cpu().numpy(), s.item(), y_ref, s_ref, 0.0, (n, ch))
         else:
             host = synth.host(dt, n, 700 + i)
             xo = x_tensor(dt, OPN[op], identity(dt, OPN[op]))

@@ -14,6 +14,7 @@ import torch
 
 import oracle
 import synth
+from gpu_util import check_axpy
 
 pytestmark = pytest.mark.gpu
 
@@ -71,8 +72,7 @@ def test_queue_axpy_parity(gpu_lib, kind, case):
     s = torch.tensor([0.25], dtype=torch.float32, device="cuda")
     om.axpy_sum_queue(kind, 0.7, x, y, s, T, P, dc, c)
     torch.cuda.synchronize()
-    assert np.array_equal(y.cpu().numpy().view(np.uint32), ref_y.view(np.uint32))
-    assert abs(float(s.item()) - ref_s) <= 1e-6 * abs(ref_s)
+    check_axpy(y.cpu().numpy(), s.item(), ref_y, ref_s, 0.25, (kind, AXPY[case]))
 
 
 def test_queue_axpy_2pow26_all_chunks_agree(gpu_lib):

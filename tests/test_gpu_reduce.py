@@ -224,12 +224,30 @@ def test_separate_streams(gpu_lib):
 
 
 def test_empty_region_sweep(gpu_lib):
+    """Empty regions over N in {0, 1, 2, 4, ..., 1024} (plus two large trip counts) for
+    T in 1..64 teams and several (P, dist_chunk, chunk) schedules: every launch must
+    count exactly N iterations through its team tree and cross-team step, and no
+    thread may find its chunks inconsistent (status bit 16)."""
     om = gpu_lib
-    for n in [0, 1, 2, 4, 16, 256, 1024]:
-        for T in (1, 8, 64):
-            om.empty_region(n, T, 256)
-            om.empty_region(n, T, 100, 3, 2)
-    torch.cuda.synchronize()
+    om.workspace_reset()
+    assert om.workspace_status() == 0
+    ns = [0] + [1 << k for k in range(11)] + [3, 1000, 1023, (1 << 40) + 12345]
+    teams = (1, 2, 3, 8, 17, 64)
+    scheds = [(256, 0, 0), (256, 0, 1), (256, 0, 7), (100, 3, 2), (64, 5, 0), (1, 1, 1),
+              (1024, 1024, 64), (33, 0, 1024)]
+    cases = [(n, T, P, dc, c) for n in ns for T in teams for (P, dc, c) in scheds
+             if not (n > 1 << 20 and dc and dc < 1024)]
+    iters = torch.zeros(len(cases), dtype=torch.int64, device="cuda")
+    for k, (n, T, P, dc, c) in enumerate(cases):
+        om.empty_region(n, T, P, dc, c, iters=iters[k:k + 1])
+    assert om.workspace_status() == 0
+    got = iters.cpu().tolist()
+    bad = [(case, g) for case, g in zip(cases, got) if g != case[0]]
+    assert not bad, bad[:10]
+    # without a counter the region still runs the whole protocol
+    for T in (1, 64):
+        om.empty_region(1024, T, 256)
+    assert om.workspace_status() == 0
 
 
 def test_plain_launches_under_caller_graph_capture(gpu_lib):
@@ -265,6 +283,47 @@ def test_plain_launches_under_caller_graph_capture(gpu_lib):
         g.replay()
         torch.cuda.synchronize()
         assert (xs.item(), xi.item(), xm.item()) == want, rep
+    assert om.workspace_status(stream=s) == 0
+
+
+def test_captured_graph_survives_workspace_growth(gpu_lib):
+    """A graph captured at 777 teams, then an eager 8000-team call on the same stream
+    (which outgrows the stream's workspace): the replays after the growth still run on
+    the workspace they captured, which the library keeps until omprt_finalize, and
+    reproduce the eager result."""
+    om = gpu_lib
+    f = to_device(synth.f32_normal(2_000_003, 34), synth.F32)
+    s = torch.cuda.Stream()
+    om.workspace_reserve(777, stream=s)
+    xs = torch.zeros(1, dtype=torch.float32, device="cuda")
+    cfg = {"teams": 777, "threads": 256}
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        om.reduce(f, "sum", xs, config=cfg)
+    torch.cuda.synchronize()
+    want = xs.item()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        om.reduce(f, "sum", xs, config=cfg)
+    xs.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    assert xs.item() == want
+    x2 = torch.zeros(1, dtype=torch.float32, device="cuda")
+    with torch.cuda.stream(s):
+        om.reduce(f, "sum", x2, config={"teams": 8000, "threads": 256})
+    torch.cuda.synchronize()
+    ref, sabs = oracle_value(to_host(f), synth.F32, "sum", 0.0)
+    check_value(x2.item(), ref, sabs, synth.F32, "sum", "8000 teams")
+    for rep in range(5):
+        xs.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert xs.item() == want, rep
+        with torch.cuda.stream(s):       # eager work on the grown workspace in between
+            om.reduce(f, "sum", x2, config={"teams": 8000, "threads": 256})
     assert om.workspace_status(stream=s) == 0
 
 

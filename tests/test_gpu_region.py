@@ -12,7 +12,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import TOL_F32
+from gpu_util import check_axpy
 
 pytestmark = pytest.mark.gpu
 A = 0.7
@@ -28,11 +28,8 @@ def _run(om, x_h, y_h, teams, threads, dc, c1, c2, nowait, s0=0.0, xoff=0, yoff=
     om.region_axpy_sum(A, xd[xoff:xoff + n], yd[yoff:yoff + n], s, teams, threads, dc, c1, c2, nowait)
     torch.cuda.synchronize()
     y_ref, s_ref = oracle.axpy_sum(A, x_h, y_h, s0)
-    got_y = yd[yoff:yoff + n].cpu().numpy()
     case = (n, teams, threads, dc, c1, c2, nowait)
-    assert np.array_equal(got_y.view(np.uint32), y_ref.view(np.uint32)), case
-    if s_ref != 0:
-        assert abs(s.item() - s_ref) <= TOL_F32 * abs(s_ref), (case, s.item(), s_ref)
+    check_axpy(yd[yoff:yoff + n].cpu().numpy(), s.item(), y_ref, s_ref, s0, case)
     assert om.workspace_status() == 0, case
 
 

@@ -108,7 +108,11 @@ def test_regret_and_tau_bookkeeping():
 
 
 def test_class_grid_matches_runtime_rule():
-    assert len(tune.CLASSES) == 32 and len(set(tune.CLASSES)) == 32
+    assert len(tune.CLASSES) == 64 and len(set(tune.CLASSES)) == 64
+    assert {c[2] for c in tune.CLASSES} == {8, 16} and {c[3] for c in tune.CLASSES} == {2, 4}
+    # 8-byte loads need twice the teams of 16-byte ones for the same small input
+    assert tune.class_teams((8, 256, 8, 4), 4096, 4, CUS) == 8
+    assert tune.class_teams((8, 256, 16, 4), 4096, 4, CUS) == 4
     assert tune.class_teams((8, 256, 16, 4), 10, 4, CUS) == 1
     assert tune.class_teams((8, 256, 16, 4), 1 << 30, 4, CUS) == 8 * CUS
     assert tune.class_teams((1, 1024, 16, 2), 1 << 30, 12, CUS) == CUS
