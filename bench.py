@@ -872,7 +872,13 @@ def main():
                     help="only run 3 device copies of 2^28 fp32 (1 GiB read + 1 GiB written), "
                          "the reference for scaling HBM byte counters")
     ap.add_argument("--only-axpy", type=int, nargs=2, metavar=("TEAMS", "CHUNK"), default=None,
-                    help="only run 3 AXPY+sum launches over 2^26 with 256 threads (profiling)")
+                    help="only run 3 AXPY+sum launches over 2^26 with --threads threads "
+                         "(profiling)")
+    ap.add_argument("--threads", type=int, default=256,
+                    help="threads per team of --only-axpy (default 256)")
+    ap.add_argument("--only-exact", action="store_true",
+                    help="only run 3 fp32 and 3 int64 sums over 2^28 with every thread reducing "
+                         "exactly its schedule(static) run, default launch (profiling)")
     ap.add_argument("--only-queue", nargs=2, metavar=("KIND", "CHUNK"), default=None,
                     help="only run 3 AXPY+sum launches over 2^26 under schedule(KIND, CHUNK), "
                          "KIND dynamic or guided, default teams x 512 threads (profiling)")
@@ -893,13 +899,21 @@ def main():
               "multi-GPU exchange is not implemented)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2106_03219_amd as om
-    import synth
     om.load()
     torch.cuda.set_device(0)
+    try:
+        run(args, om, torch)
+    finally:
+        om.finalize()   # release the library's device memory before the runtime shuts down
+
+
+def run(args, om, torch):
+    import numpy as np
+
+    import synth
     stream = torch.cuda.current_stream()
 
     if args.only_axpy:
@@ -908,9 +922,21 @@ def main():
         y = synth.device(synth.F32, 1 << 26, synth.SEED_AXPY_Y)
         s = torch.zeros(1, dtype=torch.float32, device="cuda")
         for _ in range(3):
-            om.axpy_sum(0.7, x, y, s, teams, 256, 0, chunk)
+            om.axpy_sum(0.7, x, y, s, teams, args.threads, 0, chunk)
         torch.cuda.synchronize()
-        _log(f"3 AXPY+sum launches over 2^26, {teams} teams x 256 threads, chunk {chunk}")
+        _log(f"3 AXPY+sum launches over 2^26, {teams} teams x {args.threads} threads, "
+             f"chunk {chunk}")
+        return
+
+    if args.only_exact:
+        for dt, seed in ((synth.F32, synth.SEED_F32), (synth.I64, synth.SEED_I64)):
+            t = synth.device(dt, N, seed)
+            x = torch.zeros(1, dtype=t.dtype, device="cuda")
+            for _ in range(3):
+                om.reduce(t, "sum", x, config={"flags": om.CFG_EXACT_THREAD_MAP})
+            torch.cuda.synchronize()
+            del t
+        _log("3 fp32 and 3 int64 exact-map sums over 2^28, default launch")
         return
 
     if args.only_queue:
@@ -1068,7 +1094,6 @@ def main():
         out["batched_reductions_per_s"] = extra["batched"]["reductions_per_s"]
     out.update(extra)
     print(json.dumps(out), flush=True)
-    om.finalize()   # release the library's device memory before the runtime shuts down
 
 
 if __name__ == "__main__":

@@ -4,6 +4,7 @@
 // (dynamic / guided) kernels.
 #pragma once
 #include "device.h"
+#include "lines.h"
 
 namespace omprt {
 
@@ -252,6 +253,102 @@ __device__ __forceinline__ void axpy_stride(float a, const float* __restrict__ x
         for (int u = 0; u < U; ++u) comp_add(acc, yy[u]);
     }
     for (; i < hi; i += P) axpy_elem(a, x, y, i, acc);
+}
+
+// Lane runs through LDS (lines.h), wave-collective: lane p owns np lines
+// of 32 elements starting at element `mine` of its run (y + mine on a
+// 128-byte boundary, x co-aligned with y to 16 bytes); np is the same on
+// every lane.  Each pass loads one line of x and of y per lane, eight lanes
+// a line, into LDS; the owner runs y[i] <- fmaf(a, x[i], y[i]) and its sum
+// over its line from LDS in increasing i, and the wave stores the updated
+// lines back eight lanes a line.  Loads run two passes ahead (line_passes),
+// so a wave keeps 32 KiB in flight through the LDS work of a pass.
+struct AxpyLines {
+    static constexpr int64_t kLine = kLineBytes / 4;
+    float a;
+    const float* __restrict__ x;
+    float* __restrict__ y;
+    f32x4* __restrict__ xs;
+    f32x4* __restrict__ ys;
+    ff_t* acc;
+    int64_t src[8];
+    f32x4 vx[2][8], vy[2][8];
+
+    template <int SET>
+    __device__ __forceinline__ void load(int64_t q) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            vx[SET][k] = __builtin_nontemporal_load(
+                reinterpret_cast<const f32x4*>(x + src[k] + q * kLine));
+            vy[SET][k] = __builtin_nontemporal_load(
+                reinterpret_cast<const f32x4*>(y + src[k] + q * kLine));
+        }
+    }
+    template <int SET>
+    __device__ __forceinline__ void pass(int64_t q, int64_t np) {
+        const int lane = threadIdx.x & (kWave - 1);
+        const int sw = line_swz(lane);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            xs[kWave * k + lane] = vx[SET][k];
+            ys[kWave * k + lane] = vy[SET][k];
+        }
+        if (q + 2 < np) load<SET>(q + 2);
+        wave_lds_order();
+#pragma unroll
+        for (int b = 0; b < kLineSlots; ++b) {
+            const int slot = kLineSlots * lane + (b ^ sw);
+            const f32x4 xx = xs[slot];
+            f32x4 yy = ys[slot];
+            yy.x = __builtin_fmaf(a, xx.x, yy.x);
+            yy.y = __builtin_fmaf(a, xx.y, yy.y);
+            yy.z = __builtin_fmaf(a, xx.z, yy.z);
+            yy.w = __builtin_fmaf(a, xx.w, yy.w);
+            ys[slot] = yy;
+            comp_add(*acc, yy.x);
+            comp_add(*acc, yy.y);
+            comp_add(*acc, yy.z);
+            comp_add(*acc, yy.w);
+        }
+        wave_lds_order();
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            __builtin_nontemporal_store(ys[kWave * k + lane],
+                                        reinterpret_cast<f32x4*>(y + src[k] + q * kLine));
+        wave_lds_order();
+    }
+};
+
+__device__ __forceinline__ void axpy_lines(float a, const float* __restrict__ x,
+                                           float* __restrict__ y, int64_t mine, int64_t np,
+                                           f32x4* __restrict__ xs, f32x4* __restrict__ ys,
+                                           ff_t& acc) {
+    AxpyLines f;
+    f.a = a;
+    f.x = x;
+    f.y = y;
+    f.xs = xs;
+    f.ys = ys;
+    f.acc = &acc;
+    line_sources<4>(mine, f.src);
+    line_passes(f, np);
+}
+
+// One run [lo, hi) of the calling lane, wave-collective (every lane of the
+// wave calls it, with its own run): the part before y's next line boundary
+// by the lane alone, then as many whole lines as every lane of the wave has
+// through axpy_lines, then the rest by the lane alone.  A lane's iterations
+// stay in increasing order.
+__device__ __forceinline__ void axpy_run_lines(float a, const float* __restrict__ x,
+                                               float* __restrict__ y, int64_t lo, int64_t hi,
+                                               f32x4* __restrict__ xs, f32x4* __restrict__ ys,
+                                               ff_t& acc) {
+    int64_t l0, np;
+    run_lines<4>(y, lo, hi, l0, np);
+    if (l0 > lo) axpy_range(a, x, y, lo, l0, acc);
+    axpy_lines(a, x, y, l0, np, xs, ys, acc);
+    const int64_t r = l0 + np * (kLineBytes / 4);
+    if (r < hi) axpy_range(a, x, y, r, hi, acc);
 }
 
 // End of the region: the team tree, the cross-team publish and last-team

@@ -5,18 +5,24 @@
 // the block, in increasing order.  The plain kernel instead lets a team's
 // lanes read interleaved 16-byte vectors -- allowed because a reduction
 // body cannot tell which thread ran an iteration -- and that is what keeps
-// its loads coalesced; here each lane loads its own run (16-byte vectors,
-// four in flight), so neighbouring lanes read m/P elements apart.
+// its loads coalesced.  Here neighbouring lanes' runs lie m/P elements
+// apart; for teams of whole waves the runs' whole lines pass through LDS
+// (lines.h) so that every load instruction still covers whole lines, and
+// each lane folds its own lines.  Otherwise, and for the ragged ends of the
+// runs, each lane loads its own run (16-byte vectors, four in flight).
 // Integer, max and min results equal the plain kernel's; sums may differ
 // only by rounding order.
 #include "device.h"
 #include "launch.h"
+#include "lines.h"
 #include "runtime.h"
 #include "stream.h"
 
 namespace omprt {
 
-template <int DT, int OP>
+// LINES: runs go through LDS a line at a time (8 KiB of dynamic LDS a wave;
+// the host enables it for teams of whole waves).
+template <int DT, int OP, bool LINES>
 __global__ __launch_bounds__(1024) void reduce_exact_kernel(
     const typename DType<DT>::S* __restrict__ in, int64_t n,
     typename Red<DT, OP>::Out* __restrict__ x, CrossTeam ct) {
@@ -27,6 +33,7 @@ __global__ __launch_bounds__(1024) void reduce_exact_kernel(
     using Vec = typename L::T;
     constexpr int PER = L::PER;
     constexpr int U = 4;
+    extern __shared__ u32x4 stage_words[];
     __shared__ Acc lds_slots[kMaxWaves];
     __shared__ int s_last;
     const int64_t T = gridDim.x;
@@ -34,11 +41,23 @@ __global__ __launch_bounds__(1024) void reduce_exact_kernel(
     const uint32_t epoch = T > 1 ? read_epoch(ct.epoch) : 0u;
     const Range blk = bal_share(n, T, blockIdx.x);
     const Range own = bal_share(blk.hi - blk.lo, blockDim.x, tid);
-    const int64_t lo = blk.lo + own.lo, hi = blk.lo + own.hi;
+    int64_t lo = blk.lo + own.lo;
+    const int64_t hi = blk.lo + own.hi;
 
     Acc acc[R::kNA];
 #pragma unroll
     for (int i = 0; i < R::kNA; ++i) acc[i] = R::identity();
+    if (LINES) {
+        // the part before the next line boundary by the lane alone, then as
+        // many whole lines as every lane of the wave has, through LDS; the
+        // rest below, by the lane alone
+        constexpr int S = (int)sizeof(typename D::S);
+        int64_t l0, np;
+        run_lines<S>(in, lo, hi, l0, np);
+        for (int64_t i = lo; i < l0; ++i) R::elem(acc[0], D::from(in[i]));
+        line_fold<R, DT>(in, l0, np, stage_words + (size_t)(tid / kWave) * kStageSlots, acc);
+        lo = l0 + np * (kLineBytes / S);
+    }
     if (lo < hi) {
         const uintptr_t mis = reinterpret_cast<uintptr_t>(in + lo) & 15;
         int64_t head = (int64_t)(((16 - mis) & 15) / sizeof(typename D::S));
@@ -87,9 +106,22 @@ template <int DT, int OP>
 static hipError_t launch_exact_one(const void* in, int64_t n, void* x, int teams, int threads,
                                    const CrossTeamArgs& a, hipStream_t stream) {
     const CrossTeam ct{static_cast<uint64_t*>(a.slots), a.counter, a.epoch, a.status};
-    hipLaunchKernelGGL((reduce_exact_kernel<DT, OP>), dim3(teams), dim3(threads), 0, stream,
-                       static_cast<const typename DType<DT>::S*>(in), n,
-                       static_cast<typename Red<DT, OP>::Out*>(x), ct);
+    const auto* src = static_cast<const typename DType<DT>::S*>(in);
+    auto* dst = static_cast<typename Red<DT, OP>::Out*>(x);
+    if (threads % kWave != 0) {
+        hipLaunchKernelGGL((reduce_exact_kernel<DT, OP, false>), dim3(teams), dim3(threads), 0,
+                           stream, src, n, dst, ct);
+        return hipGetLastError();
+    }
+    const size_t lds = (size_t)(threads / kWave) * kStageSlots * 16;
+    if (lds > 64 * 1024) {   // past the default dynamic LDS limit: ask for it
+        const hipError_t attr = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(reduce_exact_kernel<DT, OP, true>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (attr != hipSuccess) return attr;
+    }
+    hipLaunchKernelGGL((reduce_exact_kernel<DT, OP, true>), dim3(teams), dim3(threads), lds,
+                       stream, src, n, dst, ct);
     return hipGetLastError();
 }
 

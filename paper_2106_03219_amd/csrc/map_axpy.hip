@@ -46,11 +46,20 @@ hipError_t launch_static_map(int64_t n, int teams, int threads, int64_t dist_chu
 
 // ---------------------------------------------------------------- AXPY + sum
 
-__global__ __launch_bounds__(1024) void axpy_sum_kernel(float a, const float* __restrict__ x,
-                                                        float* __restrict__ y,
-                                                        float* __restrict__ sum, int64_t n, int P,
-                                                        int64_t dc, int64_t c, CrossTeam ct) {
+// LINES: lane runs (chunk 0, or chunks of at least kLinesMinChunk) of the
+// first `lw` waves of a team go through a per-wave LDS buffer of 2 x 8 KiB
+// (x lines, y lines) in dynamic shared memory.  The host enables it when the
+// team is whole waves and x and y are co-aligned to 16 bytes, and sizes lw
+// to the waves that can have a chunk at all (later waves' lanes get none).
+constexpr int64_t kLinesMinChunk = 64;
+constexpr int kLinesWaveBytes = 2 * kStageSlots * 16;
+
+template <bool LINES>
+__global__ __launch_bounds__(LINES ? 512 : 1024) void axpy_sum_kernel(
+    float a, const float* __restrict__ x, float* __restrict__ y, float* __restrict__ sum,
+    int64_t n, int P, int64_t dc, int64_t c, int lw, CrossTeam ct) {
     using R = Red<DT_F32, OP_SUM>;
+    extern __shared__ f32x4 stage[];
     __shared__ ff_t lds_slots[kMaxWaves];
     __shared__ int s_last;
     const int64_t T = gridDim.x, k = blockIdx.x;
@@ -58,6 +67,8 @@ __global__ __launch_bounds__(1024) void axpy_sum_kernel(float a, const float* __
     const uint32_t epoch = T > 1 ? read_epoch(ct.epoch) : 0u;
     ff_t acc = R::identity();
     if (t < P) {
+        f32x4* xs = stage + (size_t)(t / kWave) * (2 * kStageSlots);
+        f32x4* ys = xs + kStageSlots;
         const int64_t nb = team_nblocks(n, T, dc, k);
         for (int64_t i = 0; i < nb; ++i) {
             const Range blk = team_block(n, T, dc, k, i);
@@ -67,7 +78,18 @@ __global__ __launch_bounds__(1024) void axpy_sum_kernel(float a, const float* __
                 continue;
             }
             const int64_t nc = thread_nchunks(m, P, c, t);
-            for (int64_t j = 0; j < nc; ++j) {
+            int64_t j = 0;
+            if (LINES && t / kWave < lw) {
+                // Rounds in which every lane of the wave has a chunk (chunk
+                // counts do not grow with the thread number, so the wave's
+                // last lane has the fewest) run through LDS.
+                const int64_t full = c == 0 ? 1 : thread_nchunks(m, P, c, t | (kWave - 1));
+                for (; j < full; ++j) {
+                    const Range ch = thread_chunk(blk.lo, m, P, c, t, j);
+                    axpy_run_lines(a, x, y, ch.lo, ch.hi, xs, ys, acc);
+                }
+            }
+            for (; j < nc; ++j) {
                 const Range ch = thread_chunk(blk.lo, m, P, c, t, j);
                 if (c > 16 || !axpy_short_run(a, x, y, ch.lo, ch.hi, acc))
                     axpy_range(a, x, y, ch.lo, ch.hi, acc);
@@ -82,8 +104,25 @@ hipError_t launch_axpy_sum(float a, const float* x, float* y, float* sum, int64_
                            hipStream_t stream) {
     const int block = (threads + kWave - 1) / kWave * kWave;
     const CrossTeam dct{static_cast<uint64_t*>(ct.slots), ct.counter, ct.epoch, ct.status};
-    hipLaunchKernelGGL(axpy_sum_kernel, dim3(teams), dim3(block), 0, stream, a, x, y, sum, n,
-                       threads, dist_chunk, chunk, dct);
+    const bool co_aligned =
+        ((reinterpret_cast<uintptr_t>(x) ^ reinterpret_cast<uintptr_t>(y)) & 15) == 0;
+    const int lw = co_aligned ? lines_waves(n, teams, threads, dist_chunk, chunk, 4,
+                                            kLinesMinChunk, 512)
+                              : 0;
+    if (lw == 0) {
+        hipLaunchKernelGGL(axpy_sum_kernel<false>, dim3(teams), dim3(block), 0, stream, a, x, y,
+                           sum, n, threads, dist_chunk, chunk, 0, dct);
+        return hipGetLastError();
+    }
+    const size_t lds = (size_t)lw * kLinesWaveBytes;
+    if (lds > 64 * 1024) {   // past the default dynamic LDS limit: ask for it
+        const hipError_t attr =
+            hipFuncSetAttribute(reinterpret_cast<const void*>(axpy_sum_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (attr != hipSuccess) return attr;
+    }
+    hipLaunchKernelGGL(axpy_sum_kernel<true>, dim3(teams), dim3(block), lds, stream, a, x, y, sum,
+                       n, threads, dist_chunk, chunk, lw, dct);
     return hipGetLastError();
 }
 

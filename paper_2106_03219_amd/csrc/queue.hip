@@ -130,14 +130,18 @@ __global__ __launch_bounds__(1024) void queue_map_kernel(QueueCfg qc, int64_t n,
 
 // ONE: dynamic chunks of one iteration (a separate instantiation, so that
 // the register-hungry run code of the other schedules does not cut its
-// occupancy: this path is bound by memory latency).
-template <bool ONE>
+// occupancy: this path is bound by memory latency).  LINES: when a whole
+// wave takes tickets and every lane's chunk of a round exists, the wave's
+// chunks (neighbouring chunk numbers, so side by side in memory) run
+// through a per-wave LDS buffer of 16 KiB (lines.h) instead of lane by lane.
+template <bool ONE, bool LINES>
 __global__ __launch_bounds__(512) void queue_axpy_kernel(QueueCfg qc, float a,
                                                           const float* __restrict__ x,
                                                           float* __restrict__ y,
                                                           float* __restrict__ sum, int64_t n,
                                                           int64_t dc, CrossTeam ct) {
     using R = Red<DT_F32, OP_SUM>;
+    extern __shared__ f32x4 stage[];
     __shared__ uint64_t queue;
     __shared__ ff_t lds_slots[kMaxWaves];
     __shared__ int s_last;
@@ -182,6 +186,15 @@ __global__ __launch_bounds__(512) void queue_axpy_kernel(QueueCfg qc, float a,
                 } else {
                     for (int j = 0; j < qc.tickets; ++j) {
                         const int64_t tk = g.first + (int64_t)j * g.stride;
+                        if (LINES && g.stride == kWave &&
+                            read_lane64((uint64_t)tk, kWave - 1) < (uint64_t)bq.nchunks) {
+                            // the whole wave holds chunks this round (chunk
+                            // numbers grow with the lane)
+                            f32x4* xs = stage + (size_t)(t / kWave) * (2 * kStageSlots);
+                            const Range ch = bq.chunk(tk);
+                            axpy_run_lines(a, xb, yb, ch.lo, ch.hi, xs, xs + kStageSlots, acc);
+                            continue;
+                        }
                         if (tk >= bq.nchunks) break;
                         const Range ch = bq.chunk(tk);
                         if (ch.hi - ch.lo > 16 || !axpy_short_run(a, xb, yb, ch.lo, ch.hi, acc))
@@ -386,13 +399,28 @@ extern "C" omprt_status omprt_axpy_sum_queue(float a, const float* d_x, float* d
                                    tickets, &qc))
         return st;
     const int block = (threads + kWave - 1) / kWave * kWave;
-    if (kind == KIND_DYNAMIC && qc.cmin == 1)
-        hipLaunchKernelGGL(queue_axpy_kernel<true>, dim3(teams), dim3(block), 0, stream, qc, a,
-                           d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
-    else
-        hipLaunchKernelGGL(queue_axpy_kernel<false>, dim3(teams), dim3(block), 0, stream, qc, a,
-                           d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
-    const hipError_t e = hipGetLastError();
+    // lines for chunks of at least 64 iterations (dynamic) and for guided
+    // chunks (they start at m / P iterations), teams of whole waves, x and y
+    // co-aligned to 16 bytes
+    const bool lines = threads % kWave == 0 && (kind == KIND_GUIDED || qc.cmin >= 64) &&
+                       ((reinterpret_cast<uintptr_t>(d_x) ^ reinterpret_cast<uintptr_t>(d_y)) & 15) == 0;
+    hipError_t e = hipSuccess;
+    if (kind == KIND_DYNAMIC && qc.cmin == 1) {
+        hipLaunchKernelGGL((queue_axpy_kernel<true, false>), dim3(teams), dim3(block), 0, stream,
+                           qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
+    } else if (!lines) {
+        hipLaunchKernelGGL((queue_axpy_kernel<false, false>), dim3(teams), dim3(block), 0, stream,
+                           qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
+    } else {
+        const size_t lds = (size_t)(threads / kWave) * 2 * kStageSlots * 16;
+        if (lds > 64 * 1024)   // past the default dynamic LDS limit: ask for it
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(queue_axpy_kernel<false, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL((queue_axpy_kernel<false, true>), dim3(teams), dim3(block), lds,
+                               stream, qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "queue axpy launch: %s", hipGetErrorString(e));
     return OMPRT_OK;
 }

@@ -10,6 +10,8 @@
 // schedule (same iteration count and chunk): every iteration goes to the
 // same thread in both, and each thread's own stores precede its loads.
 // With c1 != c2 the entry point therefore refuses nowait.
+#include <algorithm>
+
 #include "axpy.h"
 #include "device.h"
 #include "launch.h"
@@ -68,17 +70,28 @@ __device__ __forceinline__ void sum_stride(const float* __restrict__ y, int64_t 
     for (; i < hi; i += P) comp_add(acc, y[i]);
 }
 
-template <bool NOWAIT>
-__global__ __launch_bounds__(1024) void region_axpy_then_sum_kernel(
+// LINES: the lane runs of the first lw1 (loop 1) / lw2 (loop 2) waves of a
+// team go through a per-wave LDS buffer (lines.h; 16 KiB a wave of dynamic
+// shared memory).  With nowait both loops have the same schedule, so lw1 ==
+// lw2 and a wave splits every run the same way in both: the lane that loads
+// a 16-byte block of y in loop 2 is the lane that stored it in loop 1, and
+// the heads and tails of the runs stay with their owners.
+template <bool NOWAIT, bool LINES>
+__global__ __launch_bounds__(LINES ? 512 : 1024) void region_axpy_then_sum_kernel(
     float a, const float* __restrict__ x, float* __restrict__ y, float* __restrict__ sum,
-    int64_t n, int P, int64_t dc, int64_t c1, int64_t c2, CrossTeam ct) {
+    int64_t n, int P, int64_t dc, int64_t c1, int64_t c2, int lw1, int lw2, CrossTeam ct) {
     using R = Red<DT_F32, OP_SUM>;
+    using R1 = CompSum<float, 1>;
+    extern __shared__ f32x4 stage[];
     __shared__ ff_t lds_slots[kMaxWaves];
     __shared__ int s_last;
     const int64_t T = gridDim.x, k = blockIdx.x;
     const int t = threadIdx.x;
+    const int wave = t / kWave;
     const uint32_t epoch = T > 1 ? read_epoch(ct.epoch) : 0u;
     const int64_t nb = team_nblocks(n, T, dc, k);
+    f32x4* xs = stage + (size_t)wave * (2 * kStageSlots);
+    f32x4* ys = xs + kStageSlots;
     // loop 1: the AXPY update (its sum is not used here)
     if (t < P) {
         ff_t unused = R::identity();
@@ -90,7 +103,15 @@ __global__ __launch_bounds__(1024) void region_axpy_then_sum_kernel(
                 continue;
             }
             const int64_t nc = thread_nchunks(m, P, c1, t);
-            for (int64_t j = 0; j < nc; ++j) {
+            int64_t j = 0;
+            if (LINES && wave < lw1) {
+                const int64_t full = c1 == 0 ? 1 : thread_nchunks(m, P, c1, t | (kWave - 1));
+                for (; j < full; ++j) {
+                    const Range ch = thread_chunk(blk.lo, m, P, c1, t, j);
+                    axpy_run_lines(a, x, y, ch.lo, ch.hi, xs, ys, unused);
+                }
+            }
+            for (; j < nc; ++j) {
                 const Range ch = thread_chunk(blk.lo, m, P, c1, t, j);
                 if (c1 > 16 || !axpy_short_run(a, x, y, ch.lo, ch.hi, unused))
                     axpy_range(a, x, y, ch.lo, ch.hi, unused);
@@ -109,13 +130,55 @@ __global__ __launch_bounds__(1024) void region_axpy_then_sum_kernel(
                 continue;
             }
             const int64_t nc = thread_nchunks(m, P, c2, t);
-            for (int64_t j = 0; j < nc; ++j) {
+            int64_t j = 0;
+            if (LINES && wave < lw2) {
+                const int64_t full = c2 == 0 ? 1 : thread_nchunks(m, P, c2, t | (kWave - 1));
+                for (; j < full; ++j) {
+                    const Range ch = thread_chunk(blk.lo, m, P, c2, t, j);
+                    int64_t l0, np;
+                    run_lines<4>(y, ch.lo, ch.hi, l0, np);
+                    if (l0 > ch.lo) sum_range(y, ch.lo, l0, acc);
+                    line_fold<R1, DT_F32>(y, l0, np, reinterpret_cast<u32x4*>(xs), &acc);
+                    const int64_t r = l0 + np * (kLineBytes / 4);
+                    if (r < ch.hi) sum_range(y, r, ch.hi, acc);
+                }
+            }
+            for (; j < nc; ++j) {
                 const Range ch = thread_chunk(blk.lo, m, P, c2, t, j);
                 sum_range(y, ch.lo, ch.hi, acc);
             }
         }
     }
     axpy_finish_sum(acc, sum, ct, epoch, lds_slots, &s_last);
+}
+
+template <bool NOWAIT>
+static hipError_t launch_region(float a, const float* x, float* y, float* sum, int64_t n,
+                                int teams, int threads, int64_t dc, int64_t c1, int64_t c2,
+                                const CrossTeam& ct, hipStream_t stream) {
+    constexpr int64_t kMinChunk = 64;
+    const int block = (threads + kWave - 1) / kWave * kWave;
+    const bool co_aligned =
+        ((reinterpret_cast<uintptr_t>(x) ^ reinterpret_cast<uintptr_t>(y)) & 15) == 0;
+    int lw1 = co_aligned ? lines_waves(n, teams, threads, dc, c1, 4, kMinChunk, 512) : 0;
+    int lw2 = lines_waves(n, teams, threads, dc, c2, 4, kMinChunk, 512);
+    if (NOWAIT) lw1 = lw2 = std::min(lw1, lw2);   // the same split of every run in both loops
+    const int lw = std::max(lw1, lw2);
+    if (lw == 0) {
+        hipLaunchKernelGGL((region_axpy_then_sum_kernel<NOWAIT, false>), dim3(teams), dim3(block),
+                           0, stream, a, x, y, sum, n, threads, dc, c1, c2, 0, 0, ct);
+        return hipGetLastError();
+    }
+    const size_t lds = (size_t)lw * 2 * kStageSlots * 16;
+    if (lds > 64 * 1024) {   // past the default dynamic LDS limit: ask for it
+        const hipError_t attr = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(region_axpy_then_sum_kernel<NOWAIT, true>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (attr != hipSuccess) return attr;
+    }
+    hipLaunchKernelGGL((region_axpy_then_sum_kernel<NOWAIT, true>), dim3(teams), dim3(block), lds,
+                       stream, a, x, y, sum, n, threads, dc, c1, c2, lw1, lw2, ct);
+    return hipGetLastError();
 }
 
 }  // namespace omprt
@@ -156,14 +219,11 @@ extern "C" omprt_status omprt_region_axpy_sum(float a, const float* d_x, float* 
     if (omprt_status st = workspace_get(stream, teams, &ws)) return st;
     const CrossTeamArgs ca = ws->cross();
     const CrossTeam ct{static_cast<uint64_t*>(ca.slots), ca.counter, ca.epoch, ca.status};
-    const int block = (threads + kWave - 1) / kWave * kWave;
-    if (nowait)
-        hipLaunchKernelGGL(region_axpy_then_sum_kernel<true>, dim3(teams), dim3(block), 0, stream, a,
-                           d_x, d_y, d_sum, s->n, threads, s->dist_chunk, s->chunk, chunk2, ct);
-    else
-        hipLaunchKernelGGL(region_axpy_then_sum_kernel<false>, dim3(teams), dim3(block), 0, stream,
-                           a, d_x, d_y, d_sum, s->n, threads, s->dist_chunk, s->chunk, chunk2, ct);
-    const hipError_t e = hipGetLastError();
+    const hipError_t e =
+        nowait ? launch_region<true>(a, d_x, d_y, d_sum, s->n, teams, threads, s->dist_chunk,
+                                     s->chunk, chunk2, ct, stream)
+               : launch_region<false>(a, d_x, d_y, d_sum, s->n, teams, threads, s->dist_chunk,
+                                      s->chunk, chunk2, ct, stream);
     if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "region launch: %s", hipGetErrorString(e));
     return OMPRT_OK;
 }

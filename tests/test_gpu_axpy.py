@@ -33,7 +33,13 @@ def _run(om, x_h, y_h, teams, threads, dc, c, s0=0.0, xoff=0, yoff=0, config=Non
 
 SMALL = [(1, 1, 1, 0, 0), (100, 2, 64, 0, 0), (1000, 3, 9, 0, 1), (1000, 3, 9, 13, 5),
          (4099, 5, 100, 0, 7), (65537, 16, 256, 0, 64), (65537, 16, 256, 1000, 1024),
-         (100003, 128, 64, 0, 0), (100003, 0, 0, 0, 0), (5, 8, 64, 0, 0)]
+         (100003, 128, 64, 0, 0), (100003, 0, 0, 0, 0), (5, 8, 64, 0, 0),
+         # whole-wave teams with lane runs (chunk 0 or >= 64): lines through LDS,
+         # with ragged runs (heads and tails per lane), short runs (no whole
+         # line), dist_schedule blocks, a final partial round of chunks
+         (300000, 7, 256, 0, 0), (300000, 7, 512, 0, 100), ((1 << 20), 4, 128, 0, 0),
+         ((1 << 20) + 37, 3, 192, 5000, 64), (1000, 2, 256, 0, 0), (70000, 1, 512, 0, 2048),
+         ((1 << 20) + 5, 9, 448, 0, 96), (200000, 33, 64, 0, 0)]
 
 
 @pytest.mark.parametrize("n,T,P,dc,c", SMALL)
@@ -46,9 +52,12 @@ def test_axpy_small_schedules(gpu_lib, n, T, P, dc, c):
 def test_axpy_misaligned(gpu_lib):
     x = synth.f32_normal(50001, 3)
     y = synth.f32_normal(50001, 4)
-    for xo, yo in [(1, 1), (1, 2), (3, 0)]:
+    # (1, 2) and (3, 0): x and y not co-aligned; (2, 2) and (4, 0): co-aligned
+    # to 16 bytes, with line boundaries inside the runs
+    for xo, yo in [(1, 1), (1, 2), (3, 0), (2, 2), (4, 0)]:
         _run(gpu_lib, x, y, 32, 256, 0, 0, xoff=xo, yoff=yo)
         _run(gpu_lib, x, y, 32, 256, 0, 64, xoff=xo, yoff=yo)
+        _run(gpu_lib, x, y, 5, 128, 0, 1024, xoff=xo, yoff=yo)
 
 
 @pytest.fixture(scope="module")

@@ -57,7 +57,10 @@ def test_queue_map(gpu_lib, kind, sched):
 
 
 AXPY = [(1000, 3, 96, 0, 0), (100003, 13, 96, 0, 1), (100003, 13, 96, 1000, 3), (1 << 20, 64, 256, 0, 64),
-        (1 << 20, 0, 0, 0, 1), (1 << 20, 0, 0, 0, 0), (5000, 2, 130, 0, 2)]
+        (1 << 20, 0, 0, 0, 1), (1 << 20, 0, 0, 0, 0), (5000, 2, 130, 0, 2),
+        # whole-wave teams with long chunks (through LDS lines): ragged chunk
+        # sizes and block starts, distribute blocks, a final partial round
+        ((1 << 20) + 37, 5, 192, 0, 100), (300000, 7, 512, 30011, 64), ((1 << 20) + 3, 3, 128, 0, 2048)]
 
 
 @pytest.mark.parametrize("kind", ["dynamic", "guided"])

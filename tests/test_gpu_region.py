@@ -35,7 +35,10 @@ def _run(om, x_h, y_h, teams, threads, dc, c1, c2, nowait, s0=0.0, xoff=0, yoff=
 
 SCHEDS = [(1, 1, 1, 0), (100, 2, 64, 0), (1000, 3, 9, 0), (1000, 3, 9, 13), (4099, 5, 100, 0),
           (65537, 16, 256, 0), (65537, 16, 256, 1000), (100003, 128, 64, 0), (100003, 0, 0, 0),
-          (5, 8, 64, 0), (300001, 7, 1000, 0)]
+          (5, 8, 64, 0), (300001, 7, 1000, 0),
+          # whole-wave teams with lane runs of one line or more (through LDS
+          # lines): aligned and ragged runs, distribute blocks
+          ((1 << 20) + 3, 4, 256, 0), (300000, 7, 512, 0), ((1 << 20) + 37, 3, 192, 5000)]
 
 
 @pytest.mark.parametrize("n,T,P,dc", SCHEDS)
@@ -58,10 +61,12 @@ def test_barrier_different_schedules(gpu_lib, c1, c2):
 def test_misaligned(gpu_lib):
     x = synth.f32_normal(50001, 3)
     y = synth.f32_normal(50001, 4)
-    for xo, yo in [(1, 1), (1, 2), (3, 0)]:
+    # (1, 2) and (3, 0): x and y not co-aligned; (2, 2) and (4, 0): co-aligned
+    # to 16 bytes, with line boundaries inside the runs
+    for xo, yo in [(1, 1), (1, 2), (3, 0), (2, 2), (4, 0)]:
         for c in (0, 1, 64):
-            _run(gpu_lib, x, y, 32, 256, 0, c, c, True, xoff=xo, yoff=yo)
-        _run(gpu_lib, x, y, 32, 256, 0, 0, 64, False, xoff=xo, yoff=yo)
+            _run(gpu_lib, x, y, 8, 256, 0, c, c, True, xoff=xo, yoff=yo)
+        _run(gpu_lib, x, y, 8, 256, 0, 0, 64, False, xoff=xo, yoff=yo)
 
 
 @pytest.mark.parametrize("c", [0, 1, 64])
