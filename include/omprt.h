@@ -657,6 +657,27 @@ omprt_status omprt_resolve_config(int64_t n, int32_t dtype, int32_t op,
 omprt_status omprt_tune_set(int32_t dtype, int32_t op, int32_t body,
                             int32_t log2n, const omprt_config *cfg);
 
+/*
+ * omprt_reduce without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, kernels and
+ * results as omprt_reduce, but the cross-team state (counter, epoch,
+ * status, one 32-byte slot per team) lives in a fixed array of
+ * 256 + 4096 * 32 bytes (128 KiB + 256 B) of static device memory that
+ * each device holds until the process ends.  The call allocates nothing
+ * (no hipMalloc, no hipFree, no library allocation); the array's device
+ * address is looked up on the first call on each device.  Calls on one
+ * device share its array: calls that overlap on one device (on different
+ * streams, or concurrent host threads) race and must not be made.  The
+ * array keeps the state of the last call, which is what the next call
+ * needs (counter back at 0, epoch advanced).
+ * Errors: those of omprt_reduce, plus INVALID when the resolved team count
+ * exceeds 4096 (the array's slots); NOMEM is never returned.
+ */
+omprt_status omprt_reduce_noalloc(const void *d_in, int64_t n, int32_t dtype,
+                                  int32_t op, void *d_x, const omprt_config *cfg,
+                                  void *hip_stream);
+
 /* ----------------------------------------------------------------------- */
 /* Runtime                                                                 */
 /* ----------------------------------------------------------------------- */

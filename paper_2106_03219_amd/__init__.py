@@ -20,7 +20,7 @@ __all__ = [
     "ATOMIC_ADD", "ATOMIC_INC", "ATOMIC_MAX", "ATOMIC_EXCHANGE", "ATOMIC_CAS",
     "mlp_param_count", "mlp_forward", "mlp_loss_grad", "mlp_adam", "model_load",
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
-    "workspace_status", "finalize", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
+    "workspace_status", "finalize", "reduce_noalloc", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
     "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "PROD", "BAND", "BOR", "BXOR", "LAND",
     "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "CFG_HIST_DIRECT", "CFG_HIST_TEAM_COPY", "CFG_EXACT_THREAD_MAP", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "region_axpy_sum", "udr_declare", "reduce_udr", "queue_chunk",
     "queue_map", "axpy_sum_queue",
@@ -132,6 +132,17 @@ def reduce(inp, op, x, config=None, stream=None, n=None):
     nn = inp.numel() if n is None else int(n)
     check(load().omprt_reduce(_ptr(inp) if nn else (inp.data_ptr() or None), nn, dtype_code(inp),
                               _op(op), _ptr(x), _cfg(config), _stream(stream)), "reduce")
+
+
+def reduce_noalloc(inp, op, x, config=None, stream=None, n=None):
+    """reduce() through the entry point that allocates nothing (cross-team state in a
+    fixed device array; at most 4096 teams; calls on one device must not overlap)."""
+    if not inp.is_contiguous():
+        raise ValueError("input must be contiguous")
+    nn = inp.numel() if n is None else int(n)
+    check(load().omprt_reduce_noalloc(_ptr(inp) if nn else (inp.data_ptr() or None), nn,
+                                      dtype_code(inp), _op(op), _ptr(x), _cfg(config),
+                                      _stream(stream)), "reduce_noalloc")
 
 
 def histogram(keys, bins, hist, config=None, stream=None):

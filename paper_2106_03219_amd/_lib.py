@@ -60,6 +60,7 @@ SIGNATURES = {
     "omprt_sched_count": (_i32, [_S, _i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "omprt_static_map": (_i32, [_S, _p, _p, _p]),
     "omprt_reduce": (_i32, [_p, _i64, _i32, _i32, _p, _C, _p]),
+    "omprt_reduce_noalloc": (_i32, [_p, _i64, _i32, _i32, _p, _C, _p]),
     "omprt_reduce_array": (_i32, [_p, _i64, _i64, _i32, _i32, _p, _C, _p]),
     "omprt_reduce_loc": (_i32, [_p, _i64, _i32, _i32, _p, _p, _C, _p]),
     "omprt_reduce_multi": (_i32, [_p, _i64, _i32, _i32, _p, _p, _C, _p]),
