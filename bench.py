@@ -62,12 +62,19 @@ def cpu_baseline(f_host, i_host, passes: int):
     are also what the GPU step is checked against."""
     import numpy as np
     import oracle
-    t0 = time.perf_counter()
-    for _ in range(passes):
-        ref_s, abs_s = oracle.reduce_fp(f_host, "sum", 0.0, want_abs=True)
-        ref_m = oracle.reduce_fp(f_host, "max", -np.inf)
-        ref_i = oracle.reduce_int(i_host, "sum", 0)
-    dt = time.perf_counter() - t0
+    # pinned to one core of those this process may use (the oracle is serial C)
+    allowed = os.sched_getaffinity(0)
+    core = min(allowed)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        for _ in range(passes):
+            ref_s, abs_s = oracle.reduce_fp(f_host, "sum", 0.0, want_abs=True)
+            ref_m = oracle.reduce_fp(f_host, "max", -np.inf)
+            ref_i = oracle.reduce_int(i_host, "sum", 0)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, allowed)
     step_bytes = f_host.nbytes * 2 + i_host.nbytes
     cpu_model = "unknown"
     try:
@@ -81,8 +88,8 @@ def cpu_baseline(f_host, i_host, passes: int):
     baseline = {"value": round(passes * step_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
                 "kind": "oracle",
                 "sample": f"{passes} serial passes of the full step (fp32 sum, fp32 max, int64 "
-                          f"sum over 2^28 each; {dt:.1f} s), FP64 Neumaier sums; 1 core of "
-                          f"{os.cpu_count()} ({cpu_model})"}
+                          f"sum over 2^28 each; {dt:.1f} s), FP64 Neumaier sums; pinned to "
+                          f"core {core}, 1 core of {len(allowed)} available ({cpu_model})"}
     return baseline, (ref_s, abs_s, ref_m, ref_i)
 
 
@@ -243,7 +250,7 @@ def bench_axpy(om, torch, leg=None):
 
     table = {}
     for c in (0, 1, 64, 1024):
-        for T in (64, 256, 1024, 4096):
+        for T in (64, 128, 256, 512, 1024, 2048, 4096):
             for P in (256, 512):
                 checked(T, P, c)
                 us = _time_us(lambda: om.axpy_sum(0.7, x, y, s, T, P, 0, c), torch)
@@ -864,7 +871,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-passes", type=int, default=3)
+    ap.add_argument("--cpu-passes", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the AXPY, latency, batched, atomics, array and picker measurements")
