@@ -338,8 +338,10 @@ def bench_loc_hist(om, torch):
 
 
 def bench_hist(om, torch, bin_counts, g=None):
-    """Histograms of 2^28 uniform int32 keys: the default strategy and atomics on hist
-    (HIST_DIRECT), each checked against torch.bincount."""
+    """Histograms of 2^28 uniform int32 keys: the default strategy, atomics on hist
+    (HIST_DIRECT) and, where they apply, range-by-range LDS copies (HIST_RANGES, up to 32
+    ranges of 40 704 bins) and the partition by bin range (HIST_PARTITION, up to 8 388 608
+    bins), each checked against torch.bincount."""
     n = 1 << 28
     if g is None:
         g = torch.Generator(device="cuda")
@@ -349,7 +351,12 @@ def bench_hist(om, torch, bin_counts, g=None):
         k = torch.randint(0, bins, (n,), device="cuda", dtype=torch.int32, generator=g)
         want = torch.bincount(k.long(), minlength=bins)
         h = torch.zeros(bins, dtype=torch.int32, device="cuda")
-        for name, cfg in (("", None), ("_direct", {"flags": om.CFG_HIST_DIRECT})):
+        forms = [("", None), ("_direct", {"flags": om.CFG_HIST_DIRECT})]
+        if 40704 < bins <= 32 * 40704:
+            forms.append(("_ranges", {"flags": om.CFG_HIST_RANGES}))
+        if 40704 < bins <= 8388608:
+            forms.append(("_partition", {"flags": om.CFG_HIST_PARTITION}))
+        for name, cfg in forms:
             h.zero_()
             om.histogram(k, bins, h, config=cfg)
             torch.cuda.synchronize()
@@ -974,7 +981,8 @@ def run(args, om, torch):
         return
 
     if args.only_hist:
-        bins = (256, 4096, 16257, 40704, 40705, 100000, 260096, 1 << 20, 1302529, 1 << 24)
+        bins = (256, 4096, 16257, 40704, 40705, 81409, 100000, 260096, 1 << 20, 1302529, 1 << 23,
+                1 << 24)
         print(json.dumps({"histogram": bench_hist(om, torch, bins)}), flush=True)
         return
 

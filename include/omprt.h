@@ -122,6 +122,12 @@ typedef struct {
                                           atomics on hist */
 #define OMPRT_CFG_HIST_DIRECT 0x8u     /* histogram: atomics on hist for any bin
                                           count (no team copy) */
+#define OMPRT_CFG_HIST_PARTITION 0x20u  /* histogram: partition the keys by bin
+                                          range first, then count each range in
+                                          LDS (up to 8 388 608 bins) */
+#define OMPRT_CFG_HIST_RANGES 0x40u     /* histogram: count the bin ranges one by
+                                          one, each reading every key (up to
+                                          32 ranges; beyond, atomics on hist) */
 #define OMPRT_CFG_EXACT_THREAD_MAP 0x10u /* omprt_reduce (sum / max / min): every
                                             thread reduces exactly its
                                             schedule(static) run of the team's
@@ -234,14 +240,22 @@ omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
  * runtime's team-shared allocation, counts its balanced block of keys into
  * it with atomic adds and adds the copy into d_hist.  Up to the LDS one
  * workgroup may take (40 704 bins on gfx950's 160 KiB) the copy is in LDS;
- * up to 32 times that, the bins are cut into ranges of that size, each team
- * counting the keys of one range (every key is read once per range);
- * beyond, every key is an atomic add on d_hist itself (no copy).  cfg->flags OMPRT_CFG_HIST_TEAM_COPY keeps team copies past the
- * ranges, each a slice of a global pool the library keeps per stream
- * (team-shared allocation falling back from LDS; atomics at L2);
- * OMPRT_CFG_HIST_DIRECT takes atomics on d_hist for any bin count.  cfg:
+ * up to four times that, the bins are cut into ranges of that size, each
+ * team counting the keys of one range (every key is read once per range); up to
+ * 8 388 608 bins the keys are first partitioned by bin range (ranges of
+ * 32 768 bins: counts per range, a prefix sum, a scatter of each key's
+ * 16-bit place within its range into a buffer of the library's pool), then
+ * each range's places are counted in an LDS copy of that range; beyond,
+ * every key is an atomic add on d_hist itself (no copy).  cfg->flags:
+ * OMPRT_CFG_HIST_RANGES counts range by range up to 32 ranges;
+ * OMPRT_CFG_HIST_PARTITION partitions for any bin count up to 8 388 608;
+ * OMPRT_CFG_HIST_TEAM_COPY keeps team copies past the ranges, each a slice
+ * of a global pool the library keeps per stream (team-shared allocation
+ * falling back from LDS; atomics at L2); OMPRT_CFG_HIST_DIRECT takes
+ * atomics on d_hist for any bin count; at most one of them.  cfg:
  * num_teams (default two per compute unit), threads_per_team (default
- * 512), unroll 1, 2 or 4 (default 4).  bins 1..2^28.
+ * 512; the partitioned passes always take 512), unroll 1, 2 or 4 (default
+ * 4).  bins 1..2^28.
  */
 omprt_status omprt_histogram(const int32_t *d_keys, int64_t n, int32_t bins,
                              int32_t *d_hist, const omprt_config *cfg,
@@ -629,6 +643,19 @@ omprt_status omprt_mlp_adam(float *d_params, float *d_m, float *d_v,
                             const float *d_grads, int64_t n, int32_t step,
                             float lr, float beta1, float beta2, float eps,
                             void *hip_stream);
+
+/*
+ * The same Adam step with its step number in device memory: *d_step holds
+ * the number of updates made so far (0 before the first); the step uses
+ * t = *d_step + 1 and leaves *d_step = t.  Nothing depends on host values
+ * that change from step to step, so a captured HIP graph of training steps
+ * can be replayed.  The update equals omprt_mlp_adam's at step t bit for
+ * bit.  Stream-ordered; d_step 4-byte aligned.
+ */
+omprt_status omprt_mlp_adam_counted(float *d_params, float *d_m, float *d_v,
+                                    const float *d_grads, int64_t n, int32_t *d_step,
+                                    float lr, float beta1, float beta2, float eps,
+                                    void *hip_stream);
 
 /*
  * Load (path != NULL) or unload (path == NULL) the learned picker used when

@@ -11,18 +11,18 @@ import ctypes
 
 from . import _lib
 from ._lib import (ATOMIC_ADD, ATOMIC_CAS, ATOMIC_EXCHANGE, ATOMIC_INC, ATOMIC_MAX, BAND, BF16,
-                   BOR, BXOR, CFG_EXACT_THREAD_MAP, CFG_HIST_DIRECT, CFG_HIST_TEAM_COPY, CFG_NO_MODEL, CFG_STATIC_TILES, F32, F64, I32, I64, LAND, LOR, MAX,
+                   BOR, BXOR, CFG_EXACT_THREAD_MAP, CFG_HIST_DIRECT, CFG_HIST_PARTITION, CFG_HIST_RANGES, CFG_HIST_TEAM_COPY, CFG_NO_MODEL, CFG_STATIC_TILES, F32, F64, I32, I64, LAND, LOR, MAX,
                    MIN, PROD, SUM, Config, MlpDims, OmprtError, Sched, Segment, check)
 
 __all__ = [
     "load", "version", "for_static_bounds", "sched_count", "static_map", "reduce",
     "reduce_batched", "reduce_each", "make_segments", "axpy_sum", "empty_region", "atomic_apply",
     "ATOMIC_ADD", "ATOMIC_INC", "ATOMIC_MAX", "ATOMIC_EXCHANGE", "ATOMIC_CAS",
-    "mlp_param_count", "mlp_forward", "mlp_loss_grad", "mlp_adam", "model_load",
+    "mlp_param_count", "mlp_forward", "mlp_loss_grad", "mlp_adam", "mlp_adam_counted", "model_load",
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
     "workspace_status", "finalize", "reduce_noalloc", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
     "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "PROD", "BAND", "BOR", "BXOR", "LAND",
-    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "CFG_HIST_DIRECT", "CFG_HIST_TEAM_COPY", "CFG_EXACT_THREAD_MAP", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "region_axpy_sum", "udr_declare", "reduce_udr", "queue_chunk",
+    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "CFG_HIST_DIRECT", "CFG_HIST_TEAM_COPY", "CFG_HIST_PARTITION", "CFG_HIST_RANGES", "CFG_EXACT_THREAD_MAP", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "region_axpy_sum", "udr_declare", "reduce_udr", "queue_chunk",
     "queue_map", "axpy_sum_queue",
 ]
 
@@ -344,6 +344,14 @@ def mlp_loss_grad(dims, params, X, y, loss, grads, stream=None):
 def mlp_adam(params, m, v, grads, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     check(load().omprt_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grads), params.numel(),
                                 int(step), lr, beta1, beta2, eps, _stream(stream)), "mlp_adam")
+
+
+def mlp_adam_counted(params, m, v, grads, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                     stream=None):
+    """Adam with the step count in the int32 device tensor `step` (advanced by one)."""
+    check(load().omprt_mlp_adam_counted(_ptr(params), _ptr(m), _ptr(v), _ptr(grads),
+                                        params.numel(), _ptr(step), lr, beta1, beta2, eps,
+                                        _stream(stream)), "mlp_adam_counted")
 
 
 def model_load(path):

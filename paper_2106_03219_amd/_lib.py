@@ -21,6 +21,8 @@ CFG_STATIC_TILES = 0x2
 CFG_HIST_TEAM_COPY = 0x4
 CFG_HIST_DIRECT = 0x8
 CFG_EXACT_THREAD_MAP = 0x10
+CFG_HIST_PARTITION = 0x20
+CFG_HIST_RANGES = 0x40
 
 
 class Sched(ctypes.Structure):
@@ -82,6 +84,7 @@ SIGNATURES = {
     "omprt_mlp_forward": (_i32, [_D, _p, _p, _i32, _p, _p]),
     "omprt_mlp_loss_grad": (_i32, [_D, _p, _p, _p, _i32, _p, _p, _p]),
     "omprt_mlp_adam": (_i32, [_p, _p, _p, _p, _i64, _i32, _f32, _f32, _f32, _f32, _p]),
+    "omprt_mlp_adam_counted": (_i32, [_p, _p, _p, _p, _i64, _p, _f32, _f32, _f32, _f32, _p]),
     "omprt_model_load": (_i32, [ctypes.c_char_p]),
     "omprt_model_features": (_i32, [_i64, _i32, _i32, _i32, _i64, ctypes.POINTER(_f32)]),
     "omprt_resolve_config": (_i32, [_i64, _i32, _i32, _i32, _i64, _C, _C, ctypes.POINTER(_i32)]),

@@ -200,6 +200,338 @@ __global__ __launch_bounds__(1024) void histogram_direct_kernel(const int32_t* _
     if (tid == 0 && s_bad) __hip_atomic_fetch_or(status, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ---------------------------------------------------------------- partitioned bins
+//
+// Bins beyond one team's LDS copy, without reading the keys once per range:
+// the keys are first partitioned by range (ranges of kPartBins bins, a
+// power of two, so a key's range is key >> kPartLog2 and its place in the
+// range key & (kPartBins - 1), kept as 16 bits), then each range's keys are
+// counted in an LDS copy of that range alone.  Four kernels and a merge:
+//   count    team t counts the valid keys of its balanced block per range
+//            (LDS counters) -> cnt[r][t]
+//   scan     one workgroup: off[r][t] = exclusive prefix of cnt in (r, t)
+//            order, rstart[r] = off[r][0], rstart[R] = valid keys
+//   scatter  team t re-reads its block and writes each valid key's 16-bit
+//            place to part[off[r][t] + its rank among the team's keys of r]
+//            (rank from an LDS cursor per range)
+//   range    team (r, s) counts slice s of range r's part (S slices a range)
+//            into an LDS copy of the range's bins; with S == 1 it adds the
+//            copy into hist (it alone owns those bins), else it stores the
+//            copy as partial s of those bins
+//   merge    (S > 1) hist[b] += sum over s of partial[s][b]
+// Key traffic: read twice, 16-bit places written once and read once (3 x
+// the key bytes) against once per range for the range-by-range copies.
+constexpr int kPartLog2 = 15;
+constexpr uint32_t kPartBins = 1u << kPartLog2;   // 128 KiB of LDS counts
+constexpr uint32_t kPartMaxRanges = 256;          // 8 388 608 bins
+constexpr int kPartThreads = 512;
+
+__device__ __forceinline__ void flag_bad(bool bad, int* s_bad, uint32_t* status) {
+    if (bad) *s_bad = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && *s_bad)
+        __hip_atomic_fetch_or(status, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The valid keys of team t's balanced block of n, in order of position, to f
+// (16-byte vectors, U in flight per lane); keys outside [0, bins) set bad.
+template <int U, class F>
+__device__ __forceinline__ void part_keys(const int32_t* __restrict__ keys, int64_t n,
+                                          uint32_t bins, F&& f, bool& bad) {
+    const int tid = threadIdx.x, P = blockDim.x;
+    const Range blk = bal_share(n, gridDim.x, blockIdx.x);
+    if (blk.lo >= blk.hi) return;
+    auto one = [&](int32_t k) {
+        if ((uint32_t)k >= bins)
+            bad = true;
+        else
+            f((uint32_t)k);
+    };
+    const int64_t a = blk.lo, e = blk.hi;
+    const uintptr_t mis = reinterpret_cast<uintptr_t>(keys + a) & 15;
+    int64_t head = (int64_t)(((16 - mis) & 15) / 4);
+    if (head > e - a) head = e - a;
+    if (tid < head) one(keys[a + tid]);
+    const int64_t p0 = a + head;
+    const int64_t nv = (e - p0) / 4;
+    using i32x4 = int32_t __attribute__((ext_vector_type(4)));
+    const i32x4* __restrict__ vp = reinterpret_cast<const i32x4*>(keys + p0);
+    int64_t v = tid;
+    for (; v + (int64_t)(U - 1) * P < nv; v += (int64_t)U * P) {
+        i32x4 r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) r[u] = __builtin_nontemporal_load(vp + v + (int64_t)u * P);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) one(r[u][q]);
+    }
+    for (; v < nv; v += P) {
+        const i32x4 r = __builtin_nontemporal_load(vp + v);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) one(r[q]);
+    }
+    const int64_t t0 = p0 + nv * 4;
+    if (tid < e - t0) one(keys[t0 + tid]);
+}
+
+constexpr int kPartPerThread = 16;
+constexpr int kPartTile = kPartThreads * kPartPerThread;
+
+// LDS counters per range are kept in C copies, lane l adding to copy l % C:
+// the lanes of a wave that meet on one range then meet on up to C addresses
+// instead of one (same-address lanes of an LDS atomic are served one after
+// another).  C = kPartCopies for up to 32 ranges, fewer above (R x C <= 256:
+// the scatter scans R x C tile counts per tile, and with many ranges few
+// lanes meet anyway).
+constexpr uint32_t kPartCopies = 8;
+__host__ __device__ constexpr uint32_t part_copies(uint32_t R) {
+    return R <= 32 ? kPartCopies : R <= 64 ? 4u : R <= 128 ? 2u : 1u;
+}
+
+// Team t counts the valid keys of its balanced block per range.
+__global__ __launch_bounds__(kPartThreads) void hist_part_count_kernel(
+    const int32_t* __restrict__ keys, int64_t n, uint32_t bins, uint32_t R,
+    uint32_t* __restrict__ cnt, uint32_t* status) {
+    __shared__ uint32_t rc[kPartMaxRanges * kPartCopies];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x;
+    const uint32_t C = part_copies(R);
+    const uint32_t copy = (uint32_t)tid % C;
+    if (tid == 0) s_bad = 0;
+    for (uint32_t r = tid; r < R * C; r += blockDim.x) rc[r] = 0u;
+    __syncthreads();
+    bool bad = false;
+    part_keys<4>(keys, n, bins,
+                 [&](uint32_t k) {
+                     __hip_atomic_fetch_add(rc + (k >> kPartLog2) * C + copy, 1u,
+                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                 },
+                 bad);
+    __syncthreads();
+    for (uint32_t r = tid; r < R; r += blockDim.x) {
+        uint32_t c = 0;
+        for (uint32_t q = 0; q < C; ++q) c += rc[r * C + q];
+        cnt[(size_t)r * gridDim.x + blockIdx.x] = c;
+    }
+    flag_bad(bad, &s_bad, status);
+}
+
+// Exclusive prefix sums of E = R x T counts, one workgroup of 1024: each
+// thread takes a contiguous run of the counts, the run totals are scanned
+// through the wave shuffles and LDS, and each run is written out.
+__global__ __launch_bounds__(1024) void hist_part_scan_kernel(const uint32_t* __restrict__ cnt,
+                                                              uint32_t R, uint32_t T,
+                                                              int64_t* __restrict__ off,
+                                                              int64_t* __restrict__ rstart) {
+    __shared__ int64_t wsum[kMaxWaves];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t E = (int64_t)R * T;
+    const int64_t per = (E + blockDim.x - 1) / blockDim.x;
+    const int64_t lo = (int64_t)tid * per < E ? (int64_t)tid * per : E;
+    const int64_t hi = lo + per < E ? lo + per : E;
+    int64_t mine = 0;
+    int64_t i0 = lo;
+    for (; i0 + 8 <= hi; i0 += 8) {   // eight independent loads at a time
+        uint32_t c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) c[u] = cnt[i0 + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mine += c[u];
+    }
+    for (; i0 < hi; ++i0) mine += cnt[i0];
+    // inclusive scan of `mine` across the wave, then across the waves
+    int64_t inc = mine;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t o = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += o;
+    }
+    if (lane == kWave - 1) wsum[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        const int nw = blockDim.x / kWave;
+        int64_t w = lane < nw ? wsum[lane] : 0;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int64_t o = __shfl_up(w, d, kWave);
+            if (lane >= d) w += o;
+        }
+        if (lane < nw) wsum[lane] = w;   // inclusive totals of waves 0..lane
+    }
+    __syncthreads();
+    int64_t run = inc - mine + (wave > 0 ? wsum[wave - 1] : 0);   // exclusive start
+    for (int64_t i = lo; i < hi; i += 8) {   // counts loaded eight at a time, then written out
+        uint32_t c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) c[u] = i + u < hi ? cnt[i + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (i + u >= hi) break;
+            off[i + u] = run;
+            if ((i + u) % T == 0) rstart[(i + u) / T] = run;
+            run += c[u];
+        }
+    }
+    if (tid == blockDim.x - 1) rstart[R] = run;
+}
+
+// Scatter, a tile of kPartTile keys at a time: the tile's valid keys are
+// ranked within their range (LDS counters), the ranges' tile
+// counts scanned, and the 16-bit places sorted by range into an LDS buffer;
+// then consecutive lanes store consecutive places of one range to
+// consecutive positions of its bucket, so the stores come as contiguous runs
+// (not one 2-byte store per key anywhere in memory).  Within its part of a
+// range's bucket a team writes its keys tile by tile; the count kernel
+// fixed how many there are.
+__global__ __launch_bounds__(kPartThreads) void hist_part_scatter_kernel(
+    const int32_t* __restrict__ keys, int64_t n, uint32_t bins, uint32_t R,
+    const int64_t* __restrict__ off, uint16_t* __restrict__ part) {
+    const uint32_t C = part_copies(R);
+    __shared__ int64_t base[kPartMaxRanges];
+    __shared__ uint32_t tcnt[kPartMaxRanges * kPartCopies];       // [range][copy]
+    __shared__ uint32_t toff[kPartMaxRanges * kPartCopies + 1];   // exclusive scan of tcnt
+    __shared__ uint16_t buf_place[kPartTile];
+    __shared__ uint16_t buf_range[kPartTile];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), P = blockDim.x;
+    const uint32_t copy = (uint32_t)tid % C;
+    const uint32_t RC = R * C;
+    for (uint32_t r = tid; r < R; r += P) base[r] = off[(size_t)r * gridDim.x + blockIdx.x];
+    const Range blk = bal_share(n, gridDim.x, blockIdx.x);
+    // the next tile's keys are loaded while this one is sorted and stored
+    uint32_t kn[kPartPerThread];
+    auto load_tile = [&](int64_t t0) {
+#pragma unroll
+        for (int q = 0; q < kPartPerThread; ++q) {
+            const int64_t i = t0 + (int64_t)q * P + tid;
+            kn[q] = i < blk.hi ? (uint32_t)__builtin_nontemporal_load(keys + i) : 0xFFFFFFFFu;
+        }
+    };
+    if (blk.lo < blk.hi) load_tile(blk.lo);
+    for (int64_t t0 = blk.lo; t0 < blk.hi; t0 += kPartTile) {
+        for (uint32_t e = tid; e < RC; e += P) tcnt[e] = 0u;
+        uint32_t kr[kPartPerThread], rank[kPartPerThread];
+#pragma unroll
+        for (int q = 0; q < kPartPerThread; ++q) kr[q] = kn[q];
+        if (t0 + kPartTile < blk.hi) load_tile(t0 + kPartTile);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPartPerThread; ++q)
+            if (kr[q] < bins)
+                rank[q] = __hip_atomic_fetch_add(tcnt + (kr[q] >> kPartLog2) * C + copy, 1u,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __syncthreads();
+        if (tid < kWave) {   // exclusive scan of the tile counts in (range, copy) order, one wave
+            uint32_t carry = 0;
+            for (uint32_t c0 = 0; c0 < RC; c0 += kWave) {
+                const uint32_t e = c0 + lane;
+                const uint32_t v = e < RC ? tcnt[e] : 0u;
+                uint32_t inc = v;
+#pragma unroll
+                for (int d = 1; d < kWave; d <<= 1) {
+                    const uint32_t o = __shfl_up(inc, d, kWave);
+                    if (lane >= d) inc += o;
+                }
+                if (e < RC) toff[e] = carry + inc - v;
+                carry += __shfl(inc, kWave - 1, kWave);
+            }
+            if (lane == 0) toff[RC] = carry;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPartPerThread; ++q)
+            if (kr[q] < bins) {
+                const uint32_t r = kr[q] >> kPartLog2;
+                const uint32_t at = toff[r * C + copy] + rank[q];
+                buf_place[at] = (uint16_t)(kr[q] & (kPartBins - 1));
+                buf_range[at] = (uint16_t)r;
+            }
+        __syncthreads();
+        // a range's keys of the tile are buf[toff[r C] .. toff[(r + 1) C])
+        const uint32_t total = toff[RC];
+        for (uint32_t at = tid; at < total; at += P) {
+            const uint32_t r = buf_range[at];
+            part[base[r] + (at - toff[r * C])] = buf_place[at];
+        }
+        __syncthreads();
+        for (uint32_t r = tid; r < R; r += P) base[r] += toff[(r + 1) * C] - toff[r * C];
+        __syncthreads();
+    }
+}
+
+// Team (r, s): slice s of S of range r's places.  out is hist (S == 1) or
+// the partials, S x bins.
+__global__ __launch_bounds__(kPartThreads) void hist_part_range_kernel(
+    const uint16_t* __restrict__ part, const int64_t* __restrict__ rstart, uint32_t bins,
+    uint32_t S, uint32_t* __restrict__ out) {
+    extern __shared__ __align__(16) char arena[];
+    lds_u32* h = (lds_u32*)arena;
+    const int tid = threadIdx.x, P = blockDim.x;
+    const uint32_t r = blockIdx.x / S, s = blockIdx.x % S;
+    const uint32_t b0 = r << kPartLog2;
+    const uint32_t tb = bins - b0 < kPartBins ? bins - b0 : kPartBins;
+    for (uint32_t b = tid; b < tb; b += P) h[b] = 0u;
+    __syncthreads();
+    const Range sl = bal_share(rstart[r + 1] - rstart[r], S, s);
+    const int64_t a = rstart[r] + sl.lo, e = rstart[r] + sl.hi;
+    auto add = [&](uint32_t j) {
+        __hip_atomic_fetch_add(h + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    if (a < e) {
+        const uintptr_t mis = reinterpret_cast<uintptr_t>(part + a) & 15;
+        int64_t head = (int64_t)(((16 - mis) & 15) / 2);
+        if (head > e - a) head = e - a;
+        if (tid < head) add(part[a + tid]);
+        const int64_t p0 = a + head;
+        const int64_t nv = (e - p0) / 8;
+        using u32x4v = uint32_t __attribute__((ext_vector_type(4)));
+        const u32x4v* __restrict__ vp = reinterpret_cast<const u32x4v*>(part + p0);
+        constexpr int U = 4;
+        int64_t v = tid;
+        for (; v + (int64_t)(U - 1) * P < nv; v += (int64_t)U * P) {
+            u32x4v w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[u] = __builtin_nontemporal_load(vp + v + (int64_t)u * P);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    add(w[u][q] & 0xFFFFu);
+                    add(w[u][q] >> 16);
+                }
+        }
+        for (; v < nv; v += P) {
+            const u32x4v w = __builtin_nontemporal_load(vp + v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                add(w[q] & 0xFFFFu);
+                add(w[q] >> 16);
+            }
+        }
+        const int64_t t0 = p0 + nv * 8;
+        if (tid < e - t0) add(part[t0 + tid]);
+    }
+    __syncthreads();
+    if (S == 1) {
+        for (uint32_t b = tid; b < tb; b += P) {
+            const uint32_t c = h[b];
+            if (c) out[b0 + b] += c;
+        }
+    } else {
+        uint32_t* o = out + (size_t)s * bins + b0;
+        for (uint32_t b = tid; b < tb; b += P) o[b] = h[b];
+    }
+}
+
+__global__ void hist_part_merge_kernel(const uint32_t* __restrict__ partial, uint32_t S,
+                                       uint32_t bins, uint32_t* __restrict__ hist) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bins) return;
+    uint32_t c = 0;
+    for (uint32_t s = 0; s < S; ++s) c += partial[(size_t)s * bins + b];
+    if (c) hist[b] += c;
+}
+
 // Global pool of the team copies that do not fit LDS: per (device, stream),
 // grown on demand outside capture.
 struct Pool {
@@ -262,6 +594,63 @@ static uint32_t hist_lds_cap() {
 // 64 KiB ranges) against about 27 G keys/s for atomics on hist; 32 ranges
 // keep a 2x margin.
 constexpr uint32_t kMaxBinTiles = 32;
+// Ranges the default takes before partitioning the keys: ranges cost one
+// read of the keys each, the partition about three plus its passes' fixed
+// costs; at 2^28 uniform keys 3 ranges ran at 441 G keys/s against 267 for
+// the partition, 7 ranges at 197 against 319.
+constexpr uint32_t kDefaultMaxBinTiles = 4;
+
+// Partitioned bins (count, scan, scatter, range, merge), teams x 512
+// threads for the passes over the keys.
+static omprt_status histogram_partitioned(const int32_t* d_keys, int64_t n, uint32_t bins,
+                                          int32_t* d_hist, int teams, hipStream_t stream) {
+    const uint32_t R = (bins + kPartBins - 1) >> kPartLog2;
+    if (R > kPartMaxRanges)
+        return fail(OMPRT_ERR_INVALID, "partitioned histogram: %u bins above %u", bins,
+                    kPartMaxRanges * kPartBins);
+    const uint32_t T = (uint32_t)teams;
+    uint32_t S = (uint32_t)((2 * device_cus() + R - 1) / R);
+    S = std::min<uint32_t>(std::max<uint32_t>(S, 1u), 64u);
+    auto up = [](uint64_t b) { return (b + 255) / 256 * 256; };
+    const uint64_t b_part = up((uint64_t)n * 2), b_cnt = up((uint64_t)R * T * 4),
+                   b_off = up((uint64_t)R * T * 8), b_rs = up((uint64_t)(R + 1) * 8),
+                   b_partial = S > 1 ? up((uint64_t)S * bins * 4) : 0;
+    void* pool = nullptr;
+    if (omprt_status st = pool_get(stream, b_part + b_cnt + b_off + b_rs + b_partial, &pool))
+        return st;
+    char* p = static_cast<char*>(pool);
+    uint16_t* part = reinterpret_cast<uint16_t*>(p);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(p + b_part);
+    int64_t* off = reinterpret_cast<int64_t*>(p + b_part + b_cnt);
+    int64_t* rstart = reinterpret_cast<int64_t*>(p + b_part + b_cnt + b_off);
+    uint32_t* partial = reinterpret_cast<uint32_t*>(p + b_part + b_cnt + b_off + b_rs);
+    Workspace* ws = nullptr;
+    if (omprt_status st = workspace_get(stream, 1, &ws)) return st;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(d_hist);
+    hipLaunchKernelGGL(hist_part_count_kernel, dim3(T), dim3(kPartThreads), 0, stream, d_keys, n,
+                       bins, R, cnt, ws->status());
+    hipLaunchKernelGGL(hist_part_scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, R, T, off,
+                       rstart);
+    hipLaunchKernelGGL(hist_part_scatter_kernel, dim3(T), dim3(kPartThreads), 0, stream, d_keys,
+                       n, bins, R, off, part);
+    const uint32_t lds = std::min(bins, kPartBins) * 4;
+    if (lds > 64 * 1024) {   // past the default dynamic LDS limit: ask for it
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(hist_part_range_kernel),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return fail(OMPRT_ERR_DEVICE, "histogram: %u bytes of LDS: %s", lds,
+                        hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(hist_part_range_kernel, dim3(R * S), dim3(kPartThreads), lds, stream, part,
+                       rstart, bins, S, S > 1 ? partial : hist);
+    if (S > 1)
+        hipLaunchKernelGGL(hist_part_merge_kernel, dim3((bins + 255) / 256), dim3(256), 0, stream,
+                           partial, S, bins, hist);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "histogram launch: %s", hipGetErrorString(e));
+    return OMPRT_OK;
+}
 
 }  // namespace omprt
 
@@ -291,20 +680,35 @@ extern "C" omprt_status omprt_histogram(const int32_t* d_keys, int64_t n, int32_
         if (cfg->unroll) unroll = cfg->unroll;
     }
     const uint32_t flags = cfg ? cfg->flags : 0u;
-    if ((flags & OMPRT_CFG_HIST_DIRECT) && (flags & OMPRT_CFG_HIST_TEAM_COPY))
-        return fail(OMPRT_ERR_INVALID, "HIST_DIRECT and HIST_TEAM_COPY exclude each other");
+    const uint32_t forced = flags & (OMPRT_CFG_HIST_DIRECT | OMPRT_CFG_HIST_TEAM_COPY |
+                                     OMPRT_CFG_HIST_PARTITION | OMPRT_CFG_HIST_RANGES);
+    if (forced & (forced - 1))
+        return fail(OMPRT_ERR_INVALID,
+                    "at most one of HIST_DIRECT, HIST_TEAM_COPY, HIST_PARTITION, HIST_RANGES");
+    if ((flags & OMPRT_CFG_HIST_PARTITION) && bins > (int64_t)kPartMaxRanges * kPartBins)
+        return fail(OMPRT_ERR_INVALID, "HIST_PARTITION takes up to %u bins",
+                    kPartMaxRanges * kPartBins);
     if (n == 0) return OMPRT_OK;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    // Bins that do not fit one team's LDS are cut into up to kMaxBinTiles
-    // ranges, each counted by its own teams (every team reads its block of
-    // the keys and counts those in its range: tiles x the key traffic, at
-    // LDS atomic speed); past that, atomics on hist, or on request team
-    // copies in the global pool (atomics at L2, then a merge).
+    // Bins that do not fit one team's LDS: up to four ranges of bins, each
+    // counted by its own teams (every team reads its block of the keys and
+    // counts those in its range); from five ranges on, the keys partitioned by
+    // range first (read twice, 16-bit places written and read once), up to
+    // kPartMaxRanges x kPartBins bins (and 16 GiB of places); past that,
+    // atomics on hist.  On request: ranges up to kMaxBinTiles of them, team
+    // copies in the global pool (atomics at L2, then a merge), partitioning,
+    // or atomics on hist for any bin count.
     const uint32_t lds_bins = hist_lds_cap() / 4 / 4 * 4;
     uint32_t tiles = (uint32_t)((bins + lds_bins - 1) / lds_bins);
     uint32_t tile_bins = tiles > 1 ? (uint32_t)((bins + tiles - 1) / tiles + 3) / 4 * 4 : (uint32_t)bins;
+    const bool part_fits = bins <= (int64_t)kPartMaxRanges * kPartBins &&
+                           (uint64_t)n * 2 <= ((uint64_t)16 << 30);
+    if ((flags & OMPRT_CFG_HIST_PARTITION) ||
+        (!forced && tiles > kDefaultMaxBinTiles && part_fits))
+        return histogram_partitioned(d_keys, n, (uint32_t)bins, d_hist, teams, stream);
     const bool direct = (flags & OMPRT_CFG_HIST_DIRECT) ||
-                        (tiles > kMaxBinTiles && !(flags & OMPRT_CFG_HIST_TEAM_COPY));
+                        (tiles > kMaxBinTiles && !(flags & OMPRT_CFG_HIST_TEAM_COPY)) ||
+                        (!forced && tiles > kDefaultMaxBinTiles);
     if (direct) {
         Workspace* ws = nullptr;
         if (omprt_status st = workspace_get(stream, 1, &ws)) return st;

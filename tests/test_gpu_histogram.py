@@ -1,9 +1,11 @@
 """GPU parity of the histogram reduction (reduction(+: hist[0:bins]) with
-hist[key[i]] += 1) against the oracle, exact: bin counts from 1 to 1 400 000
+hist[key[i]] += 1) against the oracle, exact: bin counts from 1 to 9 000 000
 (team copies in LDS -- up to 40 704 bins with gfx950's 160 KiB a workgroup;
-ranges of bins, 2 to 32 of them, each in LDS; past 32 ranges, atomics on
-hist itself by default, or team copies in the
-global pool on request; atomics on hist for any bin count on request),
+two to four ranges of bins, each in LDS; from five ranges to 8 388 608 bins the
+keys partitioned by range of 32 768 bins, then each range counted in LDS;
+beyond, atomics on hist itself; on request ranges up to 32 of them, the
+partition for any bin count up to 8 388 608, team copies in the global pool,
+or atomics on hist for any bin count),
 uniform and
 single-key (fully contended) inputs, an incoming histogram taking part,
 keys out of range (skipped and flagged), several launch configurations and
@@ -16,7 +18,8 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-BINS = [1, 7, 256, 4096, 16256, 16257, 40704, 40705, 100000, 520193, 1 << 20, 1302528, 1302529]
+BINS = [1, 7, 256, 4096, 16256, 16257, 40704, 40705, 81408, 81409, 162816, 162817, 520193,
+        1 << 20, 1302528, 1302529, 8388608, 8388609]
 SIZES = [1, 1000, (1 << 20) | 5]
 
 
@@ -39,8 +42,8 @@ def test_uniform_keys(gpu_lib, bins):
         assert np.array_equal(run(gpu_lib, keys, bins, h0), want)
 
 
-@pytest.mark.parametrize("flag", ["HIST_TEAM_COPY", "HIST_DIRECT"])
-@pytest.mark.parametrize("bins", [7, 16257, 1 << 20, 1400000])
+@pytest.mark.parametrize("flag", ["HIST_TEAM_COPY", "HIST_DIRECT", "HIST_PARTITION", "HIST_RANGES"])
+@pytest.mark.parametrize("bins", [7, 16257, 32769, 1 << 20, 1400000])
 def test_forced_strategies(gpu_lib, flag, bins):
     """Team copies from the global pool (team-shared allocation falling back past LDS) and
     atomics on hist, each forced where the default would choose otherwise (the pool holds a
@@ -90,12 +93,26 @@ def test_out_of_range_keys_flagged(gpu_lib):
     with torch.cuda.stream(s):
         om.workspace_reset()
     assert om.workspace_status(stream=s) == 0
-    # the atomic strategy flags them the same way
+    # the atomic and the partitioned strategies flag them the same way
+    for flag in (om.CFG_HIST_DIRECT, om.CFG_HIST_PARTITION):
+        with torch.cuda.stream(s):
+            h.zero_()
+            om.histogram(k, 100, h, config={"flags": flag})
+        s.synchronize()
+        assert np.array_equal(h.cpu().numpy(), want)
+        assert om.workspace_status(stream=s) & 4
+        with torch.cuda.stream(s):
+            om.workspace_reset()
+    # partitioned by default: keys outside [0, 500000) among valid ones
+    big = g.integers(-50, 500050, 400001).astype(np.int32)
+    want, sk = oracle.histogram(big, 500000)
+    assert sk > 0
     with torch.cuda.stream(s):
-        h.zero_()
-        om.histogram(k, 100, h, config={"flags": om.CFG_HIST_DIRECT})
+        kb = torch.from_numpy(big).cuda()
+        hb = torch.zeros(500000, dtype=torch.int32, device="cuda")
+        om.histogram(kb, 500000, hb)
     s.synchronize()
-    assert np.array_equal(h.cpu().numpy(), want)
+    assert np.array_equal(hb.cpu().numpy(), want)
     assert om.workspace_status(stream=s) & 4
     with torch.cuda.stream(s):
         om.workspace_reset()
@@ -104,7 +121,7 @@ def test_out_of_range_keys_flagged(gpu_lib):
 def test_repeated_launches_accumulate(gpu_lib):
     om = gpu_lib
     g = np.random.Generator(np.random.PCG64(7))
-    for bins in (1000, 30000):
+    for bins in (1000, 30000, 200000):
         keys = g.integers(0, bins, 123457).astype(np.int32)
         k = torch.from_numpy(keys).cuda()
         h = torch.zeros(bins, dtype=torch.int32, device="cuda")
