@@ -31,42 +31,70 @@ __global__ void mlp_linear_kernel(const float* __restrict__ X, const float* __re
     Y[idx] = relu ? fmaxf(s, 0.0f) : s;
 }
 
-// Per row: loss_r = logsumexp(z) - z[y];  dZ[r][j] = (softmax(z)_j - [j == y]) / B
-__global__ void mlp_softmax_ce_kernel(const float* __restrict__ Z, const int32_t* __restrict__ y,
-                                      float* __restrict__ dZ, float* __restrict__ row_loss, int B,
-                                      int K) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= B) return;
-    const float* z = Z + (int64_t)r * K;
-    float mx = z[0];
-    for (int j = 1; j < K; ++j) mx = fmaxf(mx, z[j]);
+// Per row: loss_r = logsumexp(z) - z[y];  dZ[r][j] = (softmax(z)_j - [j == y]) / B.
+// One wave per row, lanes over the classes (max and sum by wave reductions).
+struct MaxPolicy {
+    using Acc = float;
+    static __device__ __forceinline__ float combine(float a, float b) { return fmaxf(a, b); }
+};
+struct AddPolicy {
+    using Acc = float;
+    static __device__ __forceinline__ float combine(float a, float b) { return a + b; }
+};
+__global__ __launch_bounds__(256) void mlp_softmax_ce_kernel(const float* __restrict__ Z,
+                                                             const int32_t* __restrict__ y,
+                                                             float* __restrict__ dZ,
+                                                             float* __restrict__ row_loss, int B,
+                                                             int K) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (r >= B) return;   // whole waves
+    const float* z = Z + r * K;
+    float mx = -INFINITY;
+    for (int j = lane; j < K; j += kWave) mx = fmaxf(mx, z[j]);
+    mx = wave_reduce<MaxPolicy>(mx);
     float den = 0.0f;
-    for (int j = 0; j < K; ++j) den += expf(z[j] - mx);
+    for (int j = lane; j < K; j += kWave) den += expf(z[j] - mx);
+    den = wave_reduce<AddPolicy>(den);
     const int lab = y[r];
-    row_loss[r] = logf(den) - (z[lab] - mx);
+    if (lane == 0) row_loss[r] = logf(den) - (z[lab] - mx);
     const float inv = 1.0f / (float)B;
-    for (int j = 0; j < K; ++j) {
+    for (int j = lane; j < K; j += kWave) {
         const float p = expf(z[j] - mx) / den;
-        dZ[(int64_t)r * K + j] = (p - (j == lab ? 1.0f : 0.0f)) * inv;
+        dZ[r * K + j] = (p - (j == lab ? 1.0f : 0.0f)) * inv;
     }
 }
 
 // GW[j][i] = sum_r D[r][j] A[r][i];  gb[j] = sum_r D[r][j]   (compensated over r;
-// the product is rounded on its own so it is not fused into the TwoSum)
-__global__ void mlp_weight_grad_kernel(const float* __restrict__ D, const float* __restrict__ A,
-                                       float* __restrict__ GW, float* __restrict__ gb, int B,
-                                       int out, int in) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= out * (in + 1)) return;
-    const int j = idx / (in + 1), i = idx % (in + 1);
+// the product is rounded on its own so it is not fused into the TwoSum).  One
+// wave per output: lane l takes rows l, l + 64, ..., and the lanes' pairs
+// combine through the wave's float-float tree.
+struct PairPolicy {
+    using Acc = ff_t;
+    static __device__ __forceinline__ ff_t combine(ff_t a, ff_t b) { return pair_add(a, b); }
+};
+__global__ __launch_bounds__(256) void mlp_weight_grad_kernel(const float* __restrict__ D,
+                                                              const float* __restrict__ A,
+                                                              float* __restrict__ GW,
+                                                              float* __restrict__ gb, int B,
+                                                              int out, int in) {
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (w >= (int64_t)out * (in + 1)) return;   // whole waves
+    const int j = (int)(w / (in + 1)), i = (int)(w % (in + 1));
     ff_t acc{0.0f, 0.0f};
     if (i == in) {
-        for (int r = 0; r < B; ++r) comp_add(acc, D[(int64_t)r * out + j]);
-        gb[j] = acc.hi + acc.lo;
+        for (int r = lane; r < B; r += kWave) comp_add(acc, D[(int64_t)r * out + j]);
     } else {
-        for (int r = 0; r < B; ++r)
+        for (int r = lane; r < B; r += kWave)
             comp_add(acc, __fmul_rn(D[(int64_t)r * out + j], A[(int64_t)r * in + i]));
-        GW[(int64_t)j * in + i] = acc.hi + acc.lo;
+    }
+    acc = wave_reduce<PairPolicy>(acc);
+    if (lane == 0) {
+        if (i == in)
+            gb[j] = acc.hi + acc.lo;
+        else
+            GW[(int64_t)j * in + i] = acc.hi + acc.lo;
     }
 }
 
@@ -106,6 +134,28 @@ __global__ void mlp_adam_kernel(float* __restrict__ w, float* __restrict__ m,
     v[i] = vi;
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
+
+// Adam with the step count in device memory: t = *step + 1 (the bias
+// corrections are computed per thread, in double as the host path does, so
+// the update is bit for bit the one omprt_mlp_adam makes at step t).
+__global__ void mlp_adam_counted_kernel(float* __restrict__ w, float* __restrict__ m,
+                                        float* __restrict__ v, const float* __restrict__ g,
+                                        int64_t n, const int32_t* __restrict__ step, float lr,
+                                        float b1, float b2, float eps) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double t = (double)step[0] + 1.0;
+    const float c1 = (float)(1.0 - pow((double)b1, t));
+    const float c2 = (float)(1.0 - pow((double)b2, t));
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void mlp_step_advance_kernel(int32_t* step) { step[0] += 1; }
 
 // ---------------------------------------------------------------- scratch
 
@@ -236,19 +286,19 @@ extern "C" omprt_status omprt_mlp_loss_grad(const omprt_mlp_dims* d, const float
                        p.b2, a2, B, (int)H1, (int)H2, 1);
     hipLaunchKernelGGL(mlp_linear_kernel, dim3(blocks(B * K, 256)), dim3(256), 0, s, a2, p.W3,
                        p.b3, z, B, (int)H2, (int)K, 0);
-    hipLaunchKernelGGL(mlp_softmax_ce_kernel, dim3(blocks(B, 64)), dim3(64), 0, s, z, d_y, dz, rl,
-                       B, (int)K);
+    hipLaunchKernelGGL(mlp_softmax_ce_kernel, dim3(blocks((int64_t)B * kWave, 256)), dim3(256), 0,
+                       s, z, d_y, dz, rl, B, (int)K);
     hipLaunchKernelGGL(mlp_mean_kernel, dim3(1), dim3(256), 0, s, rl, B, d_loss);
-    hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(blocks(K * (H2 + 1), 64)), dim3(64), 0, s, dz,
-                       a2, gW3, gb3, B, (int)K, (int)H2);
+    hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(blocks(K * (H2 + 1) * kWave, 256)), dim3(256),
+                       0, s, dz, a2, gW3, gb3, B, (int)K, (int)H2);
     hipLaunchKernelGGL(mlp_backprop_kernel, dim3(blocks(B * H2, 256)), dim3(256), 0, s, dz, p.W3,
                        a2, d2, B, (int)K, (int)H2);
-    hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(blocks(H2 * (H1 + 1), 64)), dim3(64), 0, s,
-                       d2, a1, gW2, gb2, B, (int)H2, (int)H1);
+    hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(blocks(H2 * (H1 + 1) * kWave, 256)),
+                       dim3(256), 0, s, d2, a1, gW2, gb2, B, (int)H2, (int)H1);
     hipLaunchKernelGGL(mlp_backprop_kernel, dim3(blocks(B * H1, 256)), dim3(256), 0, s, d2, p.W2,
                        a1, d1, B, (int)H2, (int)H1);
-    hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(blocks(H1 * (F + 1), 64)), dim3(64), 0, s, d1,
-                       d_X, gW1, gb1, B, (int)H1, (int)F);
+    hipLaunchKernelGGL(mlp_weight_grad_kernel, dim3(blocks(H1 * (F + 1) * kWave, 256)), dim3(256),
+                       0, s, d1, d_X, gW1, gb1, B, (int)H1, (int)F);
     OMPRT_HIP(hipGetLastError());
     return OMPRT_OK;
 }
@@ -264,6 +314,24 @@ extern "C" omprt_status omprt_mlp_adam(float* d_params, float* d_m, float* d_v,
     hipLaunchKernelGGL(mlp_adam_kernel, dim3(blocks(n, 256)), dim3(256), 0,
                        static_cast<hipStream_t>(hip_stream), d_params, d_m, d_v, d_grads, n, lr,
                        beta1, beta2, eps, c1, c2);
+    OMPRT_HIP(hipGetLastError());
+    return OMPRT_OK;
+}
+
+extern "C" omprt_status omprt_mlp_adam_counted(float* d_params, float* d_m, float* d_v,
+                                               const float* d_grads, int64_t n, int32_t* d_step,
+                                               float lr, float beta1, float beta2, float eps,
+                                               void* hip_stream) {
+    if (n < 0) return fail(OMPRT_ERR_INVALID, "n < 0");
+    if (!d_step) return fail(OMPRT_ERR_INVALID, "step counter is NULL");
+    if (n == 0) return OMPRT_OK;
+    if (!d_params || !d_m || !d_v || !d_grads) return fail(OMPRT_ERR_INVALID, "NULL pointer");
+    if (reinterpret_cast<uintptr_t>(d_step) & 3)
+        return fail(OMPRT_ERR_INVALID, "step counter not 4-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipLaunchKernelGGL(mlp_adam_counted_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, d_params,
+                       d_m, d_v, d_grads, n, d_step, lr, beta1, beta2, eps);
+    hipLaunchKernelGGL(mlp_step_advance_kernel, dim3(1), dim3(1), 0, s, d_step);
     OMPRT_HIP(hipGetLastError());
     return OMPRT_OK;
 }

@@ -19,6 +19,7 @@ import argparse
 import json
 import math
 import sys
+import time
 
 import numpy as np
 
@@ -117,7 +118,17 @@ def write_model(path, mean, scale, params, tau):
             fh.write(" ".join(f"{v:.9g}" for v in params[i:i + 8]) + "\n")
 
 
-def train(om, torch, X, y, epochs, batch, lr, seed, log=print):
+def train(om, torch, X, y, epochs, batch, lr, seed, log=print, mode="graph", times=None):
+    """Mini-batch Adam over the rows X (features, normalised) with labels y.
+
+    The rows live on the GPU; every epoch permutes them there (one index_select) so that
+    batch j is a fixed slice.  A step is omprt_mlp_loss_grad (forward, mean softmax
+    cross-entropy into a per-batch loss slot, backward) and omprt_mlp_adam_counted (the
+    step number in device memory).  mode "graph" captures one epoch's steps in a HIP graph
+    after a first eager epoch and replays it; "eager" launches the steps one by one;
+    "sync" is the plain loop (batches copied from the host, the loss read back every step).
+    All three make the same updates in the same order.  `times`, if given, collects the
+    seconds of every epoch."""
     F, H1, H2, K = DIMS
     p0 = init_params(seed)
     assert p0.size == om.mlp_param_count(*DIMS)
@@ -125,22 +136,57 @@ def train(om, torch, X, y, epochs, batch, lr, seed, log=print):
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     grads = torch.zeros_like(params)
-    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    N = len(y)
+    starts = list(range(0, N, batch))
+    sizes = torch.tensor([min(batch, N - s0) for s0 in starts], dtype=torch.float32,
+                         device="cuda")
+    losses = torch.zeros(len(starts), dtype=torch.float32, device="cuda")
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    yd = torch.from_numpy(np.ascontiguousarray(y, dtype=np.int32)).cuda()
+    Xp, yp = torch.empty_like(Xd), torch.empty_like(yd)
     g = np.random.Generator(np.random.PCG64(seed + 1))
-    step = 0
-    for ep in range(epochs):
-        order = g.permutation(len(y))
-        tot = 0.0
-        for s in range(0, len(y), batch):
-            idx = order[s:s + batch]
-            Xb = torch.from_numpy(np.ascontiguousarray(X[idx])).cuda()
-            yb = torch.from_numpy(np.ascontiguousarray(y[idx])).cuda()
-            om.mlp_loss_grad(DIMS, params, Xb, yb, loss, grads)
-            step += 1
-            om.mlp_adam(params, m, v, grads, step, lr=lr)
-            tot += loss.item() * len(idx)
-        if ep % 10 == 0 or ep == epochs - 1:
-            log(f"[train] epoch {ep} mean loss {tot / len(y):.4f}")
+
+    def steps():
+        for j, s0 in enumerate(starts):
+            s1 = min(s0 + batch, N)
+            om.mlp_loss_grad(DIMS, params, Xp[s0:s1], yp[s0:s1], losses[j:j + 1], grads)
+            om.mlp_adam_counted(params, m, v, grads, step, lr=lr)
+
+    stream = torch.cuda.Stream()
+    graph = None
+    with torch.cuda.stream(stream):
+        for ep in range(epochs):
+            t0 = time.perf_counter()
+            order = g.permutation(N)
+            if mode == "sync":
+                tot = 0.0
+                for j, s0 in enumerate(starts):
+                    idx = order[s0:s0 + batch]
+                    Xb = torch.from_numpy(np.ascontiguousarray(X[idx])).cuda()
+                    yb = torch.from_numpy(np.ascontiguousarray(y[idx])).cuda()
+                    om.mlp_loss_grad(DIMS, params, Xb, yb, losses[j:j + 1], grads)
+                    om.mlp_adam_counted(params, m, v, grads, step, lr=lr)
+                    tot += losses[j].item() * len(idx)
+            else:
+                od = torch.from_numpy(order).cuda()
+                torch.index_select(Xd, 0, od, out=Xp)
+                torch.index_select(yd, 0, od, out=yp)
+                if mode == "graph" and ep > 0 and graph is None:
+                    graph = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(graph, stream=stream):
+                        steps()
+                if graph is not None:
+                    graph.replay()
+                else:
+                    steps()
+            if times is not None:
+                stream.synchronize()
+                times.append(time.perf_counter() - t0)
+            if ep % 10 == 0 or ep == epochs - 1:
+                if mode != "sync":
+                    tot = float((losses * sizes).sum().item())
+                log(f"[train] epoch {ep} mean loss {tot / N:.4f}")
     torch.cuda.synchronize()
     return params
 
@@ -157,6 +203,8 @@ def main(argv=None):
     ap.add_argument("--tau", type=float, default=-1.0,
                     help="confidence threshold; negative = choose on the training set")
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--mode", default="graph", choices=("graph", "eager", "sync"),
+                    help="how the training steps are launched (same updates in every mode)")
     args = ap.parse_args(argv)
 
     import torch
@@ -172,7 +220,9 @@ def main(argv=None):
     scale = np.where(std > 1e-6, 1.0 / np.maximum(std, 1e-6), 1.0).astype(np.float32)
     Xn = ((Xtr - mean) * scale).astype(np.float32)
     Xhn = ((Xho - mean) * scale).astype(np.float32)
-    params = train(om, torch, Xn, ytr, args.epochs, args.batch, args.lr, args.seed)
+    ep_times = []
+    params = train(om, torch, Xn, ytr, args.epochs, args.batch, args.lr, args.seed,
+                   mode=args.mode, times=ep_times)
     pred_tr, conf_tr = predict(om, torch, params, Xn)
     pred_ho, conf_ho = predict(om, torch, params, Xhn)
     tau = choose_tau(tr, pred_tr, conf_tr) if args.tau < 0 else args.tau
@@ -183,7 +233,9 @@ def main(argv=None):
               "heldout_model_only": evaluate(ho, pred_ho),
               "heldout_fallback_fraction": float(np.mean(conf_ho < tau)),
               "tau": tau, "train_label_accuracy": float(np.mean(pred_tr == ytr)),
-              "classes": len(CLASSES), "epochs": args.epochs, "batch": args.batch, "lr": args.lr}
+              "classes": len(CLASSES), "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+              "mode": args.mode,
+              "epoch_ms_median": round(1e3 * float(np.median(ep_times[1:] or ep_times)), 3)}
     # the runtime's C++ inference must reproduce the GPU network's choice
     om.model_load(args.out)
     cus = torch.cuda.get_device_properties(0).multi_processor_count

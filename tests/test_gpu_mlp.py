@@ -76,3 +76,44 @@ def test_adam_vs_oracle(gpu_lib):
     assert _rel(wd.cpu().numpy(), w2) < 1e-6
     assert _rel(md.cpu().numpy(), m2) < 1e-6
     assert _rel(vd.cpu().numpy(), v2) < 1e-6
+
+
+def test_adam_counted_equals_adam(gpu_lib):
+    """The step number in device memory gives the update of omprt_mlp_adam at that step,
+    bit for bit, and advances the counter by one per call."""
+    om = gpu_lib
+    g = np.random.Generator(np.random.PCG64(3))
+    n = 9000
+    p = torch.from_numpy(g.standard_normal(n).astype(np.float32)).cuda()
+    a = [p.clone(), torch.zeros_like(p), torch.zeros_like(p)]
+    b = [p.clone(), torch.zeros_like(p), torch.zeros_like(p)]
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for t in range(1, 6):
+        grads = torch.from_numpy(g.standard_normal(n).astype(np.float32)).cuda()
+        om.mlp_adam(a[0], a[1], a[2], grads, t, lr=1e-2)
+        om.mlp_adam_counted(b[0], b[1], b[2], grads, step, lr=1e-2)
+        torch.cuda.synchronize()
+        for u, w in zip(a, b):
+            assert torch.equal(u.view(torch.int32), w.view(torch.int32)), t
+        assert int(step.item()) == t
+
+
+def test_training_graph_replays_match_eager(gpu_lib):
+    """One epoch of training steps captured in a HIP graph and replayed every epoch
+    (with the epoch's permutation done eagerly between replays) makes the same
+    parameters, bit for bit, as the steps launched one by one and as the plain loop
+    that copies every batch from the host and reads every loss back."""
+    from paper_2106_03219_amd import train as tr
+    om = gpu_lib
+    g = np.random.Generator(np.random.PCG64(11))
+    X = g.standard_normal((1000, 16)).astype(np.float32)
+    y = g.integers(0, tr.DIMS[3], 1000).astype(np.int32)
+    out = {}
+    for mode in ("sync", "eager", "graph"):
+        logs = []
+        p = tr.train(om, torch, X, y, epochs=4, batch=96, lr=1e-3, seed=5, mode=mode,
+                     log=logs.append)
+        out[mode] = (p.cpu().numpy(), logs)
+    for mode in ("eager", "graph"):
+        assert np.array_equal(out[mode][0].view(np.uint32), out["sync"][0].view(np.uint32)), mode
+    assert out["graph"][1][-1].split()[-1] == out["eager"][1][-1].split()[-1]
