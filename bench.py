@@ -813,11 +813,13 @@ def bench_array(om, torch, leg=None):
 def bench_learned(om, torch, count=300):
     """The learned picker on a sample of the held-out instance distribution (seed 8,
     n <= 1e8): total and geometric-mean time with the model's launches vs the built-in
-    heuristic's, each the minimum of 3 single-launch timings; both launches of an
+    heuristic's, each timed as the autotuner times its classes (GPU time a launch adds to
+    a stream of launches over inputs not in cache; min of 2 batches); both launches of an
     instance must agree (identical integer/max/min results, sums within 2e-6)."""
     import math
 
     import synth
+    from paper_2106_03219_amd.tune import Windows, calibrate_spin, time_call
     if not os.path.exists(MODEL_FILE):
         return None
     _log(f"learned picker: {count} held-out instances, model vs heuristic")
@@ -827,6 +829,8 @@ def bench_learned(om, torch, count=300):
     bufs = {dt: synth.device(dt, nmax, 60 + dt) for dt in (om.I32, om.I64, om.F32, om.BF16)}
     ybuf = synth.device(om.F32, nmax, 70)
     opn = {0: "sum", 1: "max", 2: "min"}
+    calibrate_spin(torch)
+    cursor = [0]
     om.model_load(MODEL_FILE)
     t_model = t_heur = 0.0
     logs = 0.0
@@ -837,21 +841,26 @@ def bench_learned(om, torch, count=300):
             n, dt, op, body, ch = (int(inst[k][i]) for k in ("n", "dtype", "op", "body", "chunk"))
             res = []
             tt = []
+            ebytes = 12 if body else {om.I32: 4, om.I64: 8, om.F32: 4, om.BF16: 2}[dt]
+            win = Windows(cursor, n, nmax, 3 if n * ebytes > (64 << 20) else 8)
             for cfg in (None, {"flags": om.CFG_NO_MODEL}):
                 if body:
-                    x, y = bufs[om.F32][:n], ybuf[:n]
+                    xb, yb = bufs[om.F32], ybuf
                     s = torch.zeros(1, dtype=torch.float32, device="cuda")
-                    fn = lambda: om.axpy_sum(0.7, x, y, s, 0, 0, 0, max(ch, 0), config=cfg)
-                    tt.append(_time_us(fn, torch, reps=3))
+                    fn = lambda o: om.axpy_sum(0.7, xb[o:o + n], yb[o:o + n], s, 0, 0, 0,
+                                               max(ch, 0), config=cfg)
+                    tt.append(time_call(fn, 2, torch, win))
                     res.append(None)
                 else:
-                    inp = bufs[dt][:n]
+                    full = bufs[dt]
+                    inp = full[:n]
                     xdt = torch.float32 if (dt == om.BF16 and op == 0) else inp.dtype
                     xo = torch.tensor([_identity(om, dt, opn[op])], dtype=xdt, device="cuda")
                     om.reduce(inp, opn[op], xo, config=cfg)
                     torch.cuda.synchronize()
                     res.append(float(xo.float().item()) if xo.dtype == torch.bfloat16 else xo.item())
-                    tt.append(_time_us(lambda: om.reduce(inp, opn[op], xo, config=cfg), torch, reps=3))
+                    tt.append(time_call(lambda o: om.reduce(full[o:o + n], opn[op], xo, config=cfg),
+                                        2, torch, win))
             _, src = om.resolve_config(n, dt, op, body, max(ch, 0) if body else -1)
             picked += src == 1
             if res[0] is not None:

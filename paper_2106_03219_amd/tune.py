@@ -3,7 +3,12 @@
 For each instance (n, dtype, op, body, user chunk) every class of a fixed
 candidate grid is timed on the GPU through the library (HIP events on the
 launch stream, minimum over repetitions), plus the runtime's built-in
-heuristic.  Records go to an append-only JSONL file keyed by instance id,
+heuristic.  The time of a class is the GPU time a launch adds to a stream of
+launches: a batch of launches is queued behind a spin kernel and timed as a
+whole, so host enqueueing leaves no gaps.  Each timed launch reads a window
+of the shared buffers that no launch has touched since the buffers were last
+traversed, so it streams from HBM as a reduction over resident data does
+(repeating one small input would time the 256 MB Infinity Cache instead).  Records go to an append-only JSONL file keyed by instance id,
 so an interrupted run resumes where it stopped.  The autotuner's choice for
 an instance is the argmin class; it labels the network's training data and
 judges its regret.
@@ -73,6 +78,8 @@ class Buffers:
             self.t[dt] = synth.device(dt, max_n, seed + dt)
         self.y0 = synth.device(synth.F32, max_n, seed + 10)
         self.y = self.y0.clone()
+        self.n = max_n
+        self.cursor = [0]   # next timing window (shared by every instance)
 
     def x_for(self, dtype, op):
         torch = self.torch
@@ -81,17 +88,78 @@ class Buffers:
         return torch.zeros(1, dtype=self.t[dtype].dtype, device="cuda")
 
 
-def time_call(fn, reps, torch):
-    """Min over reps of single-launch durations (HIP events on the current stream)."""
-    fn()   # warm
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(reps)]
-    for a, b in evs:
+def time_call(fn, reps, torch, windows=None):
+    """GPU time per launch of fn, min over reps (HIP events on the current stream).
+
+    Without `windows`: single launches, one event pair each.  With `windows` (a Windows of
+    the instance's length): the GPU time a launch adds to a stream of launches.  Each rep
+    enqueues a spin kernel long enough to cover the host's enqueueing, then an event, then
+    `windows.k` launches of fn back to back, then an event: the launches run from the queue
+    without host gaps, and the time per launch is the span over k.  Every launch reads a
+    window of the shared buffers that no launch has touched since the buffers were last
+    traversed, so it streams its input from HBM as a reduction over resident data does
+    (repeating one small input would time the 256 MB Infinity Cache instead).  fn then takes
+    the window's element offset."""
+    if windows is None:
+        fn()   # warm
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for a, b in evs:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return min(a.elapsed_time(b) for a, b in evs) * 1e3   # microseconds
+    fn(windows.next())   # warm (code, configuration caches)
+    best = float("inf")
+    for _ in range(reps):
+        offs = [windows.next() for _ in range(windows.k)]
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(SPIN_CYCLES[0])
         a.record()
-        fn()
+        for o in offs:
+            fn(o)
         b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e3 / len(offs))
+    return best
+
+
+# Spin-kernel cycles that keep the GPU busy for about 150 µs, enough to cover the host
+# enqueueing a batch of timed launches (set by calibrate_spin).
+SPIN_CYCLES = [1 << 20]
+
+
+def calibrate_spin(torch, target_us=150.0):
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(1 << 20)
+    a.record()
+    torch.cuda._sleep(1 << 20)
+    b.record()
     torch.cuda.synchronize()
-    return min(a.elapsed_time(b) for a, b in evs) * 1e3   # microseconds
+    us = max(a.elapsed_time(b) * 1e3, 1.0)
+    SPIN_CYCLES[0] = int((1 << 20) * target_us / us)
+    return us
+
+
+class Windows:
+    """Element offsets of successive windows of n elements in buffers of buffer_n elements:
+    a cursor that moves on by n (rounded up to 64 elements, 256 B of 4-byte data) per window
+    and wraps round at the end, so a window is read again only after the whole buffer.  k:
+    launches timed back to back (8, or 3 for inputs above 64 MiB)."""
+
+    def __init__(self, cursor, n, buffer_n, k=8):
+        self.c, self.n, self.buffer_n, self.k = cursor, n, buffer_n, k
+
+    def next(self):
+        step = (self.n + 63) // 64 * 64
+        if self.c[0] + self.n > self.buffer_n:
+            self.c[0] = 0
+        o = self.c[0]
+        self.c[0] += step
+        return o
 
 
 def _value(x):
@@ -105,7 +173,7 @@ def tune_instance(om, bufs, inst, cus, torch):
     n, dt, op, body, chunk = inst["n"], inst["dtype"], inst["op"], inst["body"], inst["chunk"]
     bpi = 12 if body else ELEM_BYTES[dt]
     big = n * bpi > (64 << 20)
-    reps = 3 if big else 5
+    reps = 2
     times = []
     cache = {}
     results = []
@@ -118,6 +186,11 @@ def tune_instance(om, bufs, inst, cus, torch):
         def axpy(teams, threads, config=None):
             return lambda: om.axpy_sum(AXPY_A, x, y, s, teams, threads, 0, c, config=config)
 
+        def axpy_at(teams, threads, config=None):   # timed launches, on rotating windows
+            return lambda o: om.axpy_sum(AXPY_A, bufs.t[2][o:o + n], bufs.y[o:o + n], s, teams,
+                                         threads, 0, c, config=config)
+        win = Windows(bufs.cursor, n, bufs.n, 3 if big else 8)
+
         def result(run):
             y.copy_(bufs.y0[:n])
             s.zero_()
@@ -127,26 +200,30 @@ def tune_instance(om, bufs, inst, cus, torch):
             cfg = class_config(cls, n, bpi, cus)
             key = (cfg["teams"], cfg["threads"])
             if key not in cache:
-                cache[key] = time_call(axpy(*key), reps, torch)
+                cache[key] = time_call(axpy_at(*key), reps, torch, win)
                 results.append([key[0], key[1], 0, 0, result(axpy(*key))])
             times.append(cache[key])
         heur = axpy(0, 0, {"flags": om.CFG_NO_MODEL})
-        t_heur = time_call(heur, reps, torch)
+        t_heur = time_call(axpy_at(0, 0, {"flags": om.CFG_NO_MODEL}), reps, torch, win)
         results.append([0, 0, 0, 0, result(heur)])
         y.copy_(bufs.y0[:n])
     else:
         inp = bufs.t[dt][:n]
+        full = bufs.t[dt]
         xo = bufs.x_for(dt, op)
+        win = Windows(bufs.cursor, n, bufs.n, 3 if big else 8)
         cfgs = []
         for cls in CLASSES:
             cfg = class_config(cls, n, bpi, cus)
             key = tuple(cfg.values())
             if key not in cache:
-                cache[key] = time_call(lambda: om.reduce(inp, op, xo, config=cfg), reps, torch)
+                cache[key] = time_call(lambda o: om.reduce(full[o:o + n], op, xo, config=cfg),
+                                       reps, torch, win)
                 cfgs.append(cfg)
             times.append(cache[key])
         hcfg, _ = om.resolve_config(n, dt, op, 0, -1, {"flags": om.CFG_NO_MODEL})
-        t_heur = time_call(lambda: om.reduce(inp, op, xo, config=hcfg), reps, torch)
+        t_heur = time_call(lambda o: om.reduce(full[o:o + n], op, xo, config=hcfg), reps, torch,
+                           win)
         cfgs.append(hcfg)
         outs = [bufs_identity(torch, dt, op) for _ in cfgs]
         for cfg, xv in zip(cfgs, outs):
@@ -196,10 +273,12 @@ def main(argv=None):
                 pass
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     max_n = int(inst["n"].max())
+    spin = calibrate_spin(torch)
     bufs = Buffers(max_n)
     t0 = time.time()
     todo = [i for i in range(args.count) if i not in done]
-    print(f"[tune] {len(done)} done, {len(todo)} to go, max n {max_n}, {cus} CUs", flush=True)
+    print(f"[tune] {len(done)} done, {len(todo)} to go, max n {max_n}, {cus} CUs, spin 2^20 "
+          f"cycles {spin:.0f} us", flush=True)
     with open(args.out, "a") as fh:
         for k, i in enumerate(todo):
             rec = {"id": i, "n": int(inst["n"][i]), "dtype": int(inst["dtype"][i]),

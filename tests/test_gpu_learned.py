@@ -3,8 +3,10 @@
 * With the trained model loaded, reductions and AXPY bodies whose launch the
   model picks still match the oracle (bit-exact integers / y, 1e-6 sums).
 * The model's picks beat the built-in heuristic on held-out instances
-  (total time over a sample of the held-out distribution), which is what
-  the trained network gains over the method without it.
+  (total time over a sample of the held-out distribution, timed as the
+  autotuner times: the GPU time a launch adds to a stream of launches over
+  inputs not in cache), which is what the trained network gains over the
+  method without it.
 """
 import os
 
@@ -59,26 +61,27 @@ def test_model_picked_launches_match_oracle(model):
     assert picked > 0
 
 
-def _total_time(om, insts, bufs, use_model):
+def _total_time(om, insts, bufs, nmax, use_model):
+    """Total over the instances of the GPU time a launch adds to a stream of launches over
+    uncached inputs -- the autotuner's own measure (tune.time_call with rotating windows)."""
+    from paper_2106_03219_amd.tune import Windows, calibrate_spin, time_call
+    calibrate_spin(torch)
+    cursor = [0]
     cfg = None if use_model else {"flags": om.CFG_NO_MODEL}
     total = 0.0
     for n, dt, op, body, ch in insts:
+        eb = 12 if body else {synth.I32: 4, synth.I64: 8, synth.F32: 4, synth.BF16: 2}[dt]
+        win = Windows(cursor, n, nmax, 3 if n * eb > (64 << 20) else 8)
         if body:
-            x, y = bufs[synth.F32][:n], bufs["y"][:n]
+            xb, yb = bufs[synth.F32], bufs["y"]
             s = torch.zeros(1, dtype=torch.float32, device="cuda")
-            fn = lambda: om.axpy_sum(0.7, x, y, s, 0, 0, 0, max(ch, 0), config=cfg)
+            fn = lambda o: om.axpy_sum(0.7, xb[o:o + n], yb[o:o + n], s, 0, 0, 0, max(ch, 0),
+                                       config=cfg)
         else:
-            inp = bufs[dt][:n]
+            full = bufs[dt]
             xo = x_tensor(dt, OPN[op], identity(dt, OPN[op]))
-            fn = lambda: om.reduce(inp, OPN[op], xo, config=cfg)
-        fn()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
-        for a, b in evs:
-            a.record()
-            fn()
-            b.record()
-        torch.cuda.synchronize()
-        total += min(a.elapsed_time(b) for a, b in evs)
+            fn = lambda o: om.reduce(full[o:o + n], OPN[op], xo, config=cfg)
+        total += time_call(fn, 2, torch, win) / 1e3
     return total
 
 
@@ -90,7 +93,7 @@ def test_model_beats_heuristic_on_heldout_sample(model):
     nmax = max(t[0] for t in insts)
     bufs = {dt: synth.device(dt, nmax, 40 + dt) for dt in (synth.I32, synth.I64, synth.F32, synth.BF16)}
     bufs["y"] = synth.device(synth.F32, nmax, 50)
-    t_model = _total_time(om, insts, bufs, True)
-    t_heur = _total_time(om, insts, bufs, False)
+    t_model = _total_time(om, insts, bufs, nmax, True)
+    t_heur = _total_time(om, insts, bufs, nmax, False)
     print(f"held-out sample: model {t_model:.2f} ms, heuristic {t_heur:.2f} ms")
     assert t_model < t_heur

@@ -116,3 +116,23 @@ def test_class_grid_matches_runtime_rule():
     assert tune.class_teams((8, 256, 16, 4), 10, 4, CUS) == 1
     assert tune.class_teams((8, 256, 16, 4), 1 << 30, 4, CUS) == 8 * CUS
     assert tune.class_teams((1, 1024, 16, 2), 1 << 30, 12, CUS) == CUS
+
+
+def test_tuner_windows_rotate_inside_the_buffer():
+    """The autotuner's timing windows: aligned to 64 elements, inside the buffer, every
+    window distinct until the cursor wraps, the cursor shared by all instances."""
+    from paper_2106_03219_amd.tune import Windows
+    cursor = [0]
+    buffer_n = 1_000_000
+    seen = []
+    for n in (1000, 12345, 64, 999_999, 1):
+        w = Windows(cursor, n, buffer_n, k=8)
+        for _ in range(50):
+            o = w.next()
+            assert o % 64 == 0 and 0 <= o and o + n <= buffer_n
+            seen.append((o, n))
+    firsts = [o for o, n in seen[:50]]
+    assert len(set(firsts)) == 50          # no window of the first instance read twice
+    assert cursor[0] > 0
+    big = Windows(cursor, buffer_n, buffer_n)
+    assert {big.next() for _ in range(5)} == {0}   # a window as large as the buffer stays at 0
