@@ -224,6 +224,7 @@ __global__ __launch_bounds__(1024) void histogram_direct_kernel(const int32_t* _
 constexpr int kPartLog2 = 15;
 constexpr uint32_t kPartBins = 1u << kPartLog2;   // 128 KiB of LDS counts
 constexpr uint32_t kPartMaxRanges = 256;          // 8 388 608 bins
+static_assert(kPartMaxRanges % 64 == 0 && kPartMaxRanges <= 1024, "one workgroup scans the ranges");
 constexpr int kPartThreads = 512;
 
 __device__ __forceinline__ void flag_bad(bool bad, int* s_bad, uint32_t* status) {
@@ -317,31 +318,13 @@ __global__ __launch_bounds__(kPartThreads) void hist_part_count_kernel(
     flag_bad(bad, &s_bad, status);
 }
 
-// Exclusive prefix sums of E = R x T counts, one workgroup of 1024: each
-// thread takes a contiguous run of the counts, the run totals are scanned
-// through the wave shuffles and LDS, and each run is written out.
-__global__ __launch_bounds__(1024) void hist_part_scan_kernel(const uint32_t* __restrict__ cnt,
-                                                              uint32_t R, uint32_t T,
-                                                              int64_t* __restrict__ off,
-                                                              int64_t* __restrict__ rstart) {
-    __shared__ int64_t wsum[kMaxWaves];
+// Inclusive scan of v over the workgroup (wave shuffles, then the wave totals
+// in LDS); returns v's inclusive prefix, *total the workgroup's sum.  Every
+// thread of the workgroup calls it; the workgroup is whole waves.
+__device__ inline int64_t block_scan_inclusive(int64_t v, int64_t* wsum, int64_t* total) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int64_t E = (int64_t)R * T;
-    const int64_t per = (E + blockDim.x - 1) / blockDim.x;
-    const int64_t lo = (int64_t)tid * per < E ? (int64_t)tid * per : E;
-    const int64_t hi = lo + per < E ? lo + per : E;
-    int64_t mine = 0;
-    int64_t i0 = lo;
-    for (; i0 + 8 <= hi; i0 += 8) {   // eight independent loads at a time
-        uint32_t c[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) c[u] = cnt[i0 + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) mine += c[u];
-    }
-    for (; i0 < hi; ++i0) mine += cnt[i0];
-    // inclusive scan of `mine` across the wave, then across the waves
-    int64_t inc = mine;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    int64_t inc = v;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
         const int64_t o = __shfl_up(inc, d, kWave);
@@ -350,7 +333,6 @@ __global__ __launch_bounds__(1024) void hist_part_scan_kernel(const uint32_t* __
     if (lane == kWave - 1) wsum[wave] = inc;
     __syncthreads();
     if (wave == 0) {
-        const int nw = blockDim.x / kWave;
         int64_t w = lane < nw ? wsum[lane] : 0;
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) {
@@ -360,20 +342,46 @@ __global__ __launch_bounds__(1024) void hist_part_scan_kernel(const uint32_t* __
         if (lane < nw) wsum[lane] = w;   // inclusive totals of waves 0..lane
     }
     __syncthreads();
-    int64_t run = inc - mine + (wave > 0 ? wsum[wave - 1] : 0);   // exclusive start
-    for (int64_t i = lo; i < hi; i += 8) {   // counts loaded eight at a time, then written out
-        uint32_t c[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) c[u] = i + u < hi ? cnt[i + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (i + u >= hi) break;
-            off[i + u] = run;
-            if ((i + u) % T == 0) rstart[(i + u) / T] = run;
-            run += c[u];
-        }
+    const int64_t r = inc + (wave > 0 ? wsum[wave - 1] : 0);
+    *total = wsum[nw - 1];
+    __syncthreads();   // wsum is reused by the next call
+    return r;
+}
+
+// Places within each range: workgroup r scans range r's T team counts
+// (cnt[r T + t], coalesced, a workgroup-wide piece at a time) into
+// off[r T + t] = the keys teams 0..t-1 put in range r, and leaves the
+// range's total in rstart[r].
+__global__ __launch_bounds__(1024) void hist_part_scan_range_kernel(const uint32_t* __restrict__ cnt,
+                                                                    uint32_t T,
+                                                                    int64_t* __restrict__ off,
+                                                                    int64_t* __restrict__ rstart) {
+    __shared__ int64_t wsum[kMaxWaves];
+    const size_t r = blockIdx.x;
+    int64_t carry = 0;
+    for (uint32_t t0 = 0; t0 < T; t0 += blockDim.x) {
+        const uint32_t t = t0 + threadIdx.x;
+        const int64_t v = t < T ? cnt[r * T + t] : 0;
+        int64_t tot = 0;
+        const int64_t inc = block_scan_inclusive(v, wsum, &tot);
+        if (t < T) off[r * T + t] = carry + inc - v;
+        carry += tot;
     }
-    if (tid == blockDim.x - 1) rstart[R] = run;
+    if (threadIdx.x == 0) rstart[r] = carry;
+}
+
+// Range starts: rstart[0..R) holds the range totals on entry and their
+// exclusive prefix sums on return, rstart[R] the number of valid keys.  One
+// workgroup; every total is read before any is written.
+__global__ __launch_bounds__(1024) void hist_part_scan_start_kernel(uint32_t R,
+                                                                    int64_t* __restrict__ rstart) {
+    __shared__ int64_t wsum[kMaxWaves];
+    const uint32_t r = threadIdx.x;   // R <= blockDim.x
+    const int64_t v = r < R ? rstart[r] : 0;
+    int64_t tot = 0;
+    const int64_t inc = block_scan_inclusive(v, wsum, &tot);
+    if (r < R) rstart[r] = inc - v;
+    if (r == 0) rstart[R] = tot;
 }
 
 // Scatter, a tile of kPartTile keys at a time: the tile's valid keys are
@@ -386,7 +394,8 @@ __global__ __launch_bounds__(1024) void hist_part_scan_kernel(const uint32_t* __
 // fixed how many there are.
 __global__ __launch_bounds__(kPartThreads) void hist_part_scatter_kernel(
     const int32_t* __restrict__ keys, int64_t n, uint32_t bins, uint32_t R,
-    const int64_t* __restrict__ off, uint16_t* __restrict__ part) {
+    const int64_t* __restrict__ off, const int64_t* __restrict__ rstart,
+    uint16_t* __restrict__ part) {
     const uint32_t C = part_copies(R);
     __shared__ int64_t base[kPartMaxRanges];
     __shared__ uint32_t tcnt[kPartMaxRanges * kPartCopies];       // [range][copy]
@@ -396,7 +405,8 @@ __global__ __launch_bounds__(kPartThreads) void hist_part_scatter_kernel(
     const int tid = threadIdx.x, lane = tid & (kWave - 1), P = blockDim.x;
     const uint32_t copy = (uint32_t)tid % C;
     const uint32_t RC = R * C;
-    for (uint32_t r = tid; r < R; r += P) base[r] = off[(size_t)r * gridDim.x + blockIdx.x];
+    for (uint32_t r = tid; r < R; r += P)
+        base[r] = rstart[r] + off[(size_t)r * gridDim.x + blockIdx.x];
     const Range blk = bal_share(n, gridDim.x, blockIdx.x);
     // the next tile's keys are loaded while this one is sorted and stored
     uint32_t kn[kPartPerThread];
@@ -629,10 +639,13 @@ static omprt_status histogram_partitioned(const int32_t* d_keys, int64_t n, uint
     uint32_t* hist = reinterpret_cast<uint32_t*>(d_hist);
     hipLaunchKernelGGL(hist_part_count_kernel, dim3(T), dim3(kPartThreads), 0, stream, d_keys, n,
                        bins, R, cnt, ws->status());
-    hipLaunchKernelGGL(hist_part_scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, R, T, off,
+    const uint32_t scan_threads = std::min<uint32_t>((T + kWave - 1) / kWave * kWave, 1024u);
+    hipLaunchKernelGGL(hist_part_scan_range_kernel, dim3(R), dim3(scan_threads), 0, stream, cnt,
+                       T, off, rstart);
+    hipLaunchKernelGGL(hist_part_scan_start_kernel, dim3(1), dim3(kPartMaxRanges), 0, stream, R,
                        rstart);
     hipLaunchKernelGGL(hist_part_scatter_kernel, dim3(T), dim3(kPartThreads), 0, stream, d_keys,
-                       n, bins, R, off, part);
+                       n, bins, R, off, rstart, part);
     const uint32_t lds = std::min(bins, kPartBins) * 4;
     if (lds > 64 * 1024) {   // past the default dynamic LDS limit: ask for it
         const hipError_t e = hipFuncSetAttribute(

@@ -130,3 +130,22 @@ def test_repeated_launches_accumulate(gpu_lib):
         torch.cuda.synchronize()
         want, _ = oracle.histogram(keys, bins)
         assert np.array_equal(h.cpu().numpy(), 50 * want)
+
+
+@pytest.mark.parametrize("bins,skew", [(1 << 20, False), (1 << 20, True), (5_000_000, True),
+                                       (8388608, False)])
+def test_partition_at_scale(gpu_lib, bins, skew):
+    """The partitioned strategy (the default from five LDS ranges to 8 388 608 bins) over
+    2^26 keys -- many tiles per team, range counts in the millions -- uniform, or skewed so
+    that most keys fall into a few ranges (a cubed uniform: the low bins take most), with
+    an incoming histogram, exact against the oracle."""
+    g = np.random.Generator(np.random.PCG64(bins + int(skew)))
+    n = 1 << 26
+    if skew:
+        keys = (g.random(n) ** 3 * bins).astype(np.int32)
+    else:
+        keys = g.integers(0, bins, n).astype(np.int32)
+    h0 = g.integers(-1000, 1000, bins).astype(np.int32)
+    want, sk = oracle.histogram(keys, bins, hist=h0)
+    assert sk == 0
+    assert np.array_equal(run(gpu_lib, keys, bins, h0), want), (bins, skew)
