@@ -149,3 +149,18 @@ def test_partition_at_scale(gpu_lib, bins, skew):
     want, sk = oracle.histogram(keys, bins, hist=h0)
     assert sk == 0
     assert np.array_equal(run(gpu_lib, keys, bins, h0), want), (bins, skew)
+
+
+@pytest.mark.parametrize("teams", [1, 7, 100, 1500, 2500])
+def test_partition_team_counts(gpu_lib, teams):
+    """The forced partition with team counts that are not whole waves of the per-range scan (1,
+    7, 100), and with more teams than one scan workgroup covers in one piece (1500, 2500: the
+    range's counts are scanned 1024 at a time with a carry), over 5 and 40 ranges."""
+    g = np.random.Generator(np.random.PCG64(teams))
+    cfg = {"flags": gpu_lib.CFG_HIST_PARTITION, "teams": teams}
+    for bins in (5 * 32768 - 3, 1302529):
+        for n in (1, 4097, 1000003):
+            keys = g.integers(0, bins, n).astype(np.int32)
+            h0 = g.integers(-1000, 1000, bins).astype(np.int32)
+            want, _ = oracle.histogram(keys, bins, hist=h0)
+            assert np.array_equal(run(gpu_lib, keys, bins, h0, cfg), want), (teams, bins, n)
