@@ -913,6 +913,9 @@ def main():
                     help="only run the two-loop region (nowait) measurements")
     ap.add_argument("--only-udr", action="store_true",
                     help="only run the user-defined reduction measurements")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="only run the batched workload (4096 segments), its forms checked "
+                         "against the oracle")
     ap.add_argument("--only-hist", action="store_true",
                     help="only run the histogram strategy sweep over bin counts")
     args = ap.parse_args()
@@ -987,6 +990,10 @@ def run(args, om, torch):
 
     if args.only_udr:
         print(json.dumps({"user_defined_reductions": bench_udr(om, torch)}), flush=True)
+        return
+
+    if args.only_batched:
+        print(json.dumps({"batched": bench_batched(om, torch, OracleLeg())}), flush=True)
         return
 
     if args.only_hist:

@@ -213,15 +213,18 @@ static omprt_status check_segments(const omprt_segment* s, int32_t count) {
     return OMPRT_OK;
 }
 
-// Defaults of the batched launch: 256 threads, 16-byte loads, unroll 4,
-// 256 KiB tiles, one workgroup per 256 threads of device capacity, ticket.
+// Defaults of the batched launch: 1024 threads, 16-byte loads, unroll 4,
+// 1 MiB tiles, one workgroup per 1024 threads of device capacity (two a
+// CU), ticket.  Over 4096 segments of 10^2..10^7 elements (16 GB) on
+// gfx950: 2.34 ms, against 2.54 with 256 threads and 256 KiB tiles, 2.37
+// with 1024 threads and 256 KiB, 2.33 with 4 MiB.
 static void batched_defaults(const omprt_config* cfg, omprt_config* out, int cus) {
     omprt_config c{};
     if (cfg) c = *cfg;
-    if (!c.threads_per_team) c.threads_per_team = 256;
+    if (!c.threads_per_team) c.threads_per_team = 1024;
     if (!c.vec_bytes) c.vec_bytes = 16;
     if (!c.unroll) c.unroll = 4;
-    if (!c.tile_kib) c.tile_kib = 256;
+    if (!c.tile_kib) c.tile_kib = 1024;
     if (!c.num_teams) c.num_teams = cus * (2048 / c.threads_per_team);
     c.flags &= OMPRT_CFG_STATIC_TILES;
     *out = c;
