@@ -340,8 +340,9 @@ def bench_loc_hist(om, torch):
 def bench_hist(om, torch, bin_counts, g=None):
     """Histograms of 2^28 uniform int32 keys: the default strategy, atomics on hist
     (HIST_DIRECT) and, where they apply, range-by-range LDS copies (HIST_RANGES, up to 32
-    ranges of 40 704 bins) and the partition by bin range (HIST_PARTITION, up to 8 388 608
-    bins), each checked against torch.bincount."""
+    ranges of 40 704 bins), the partition by bin range across teams (HIST_PARTITION, up to
+    8 388 608 bins) and the per-tile sort by bin range (HIST_TILE_SORT, up to 1 048 576 bins),
+    each checked against torch.bincount."""
     n = 1 << 28
     if g is None:
         g = torch.Generator(device="cuda")
@@ -356,6 +357,8 @@ def bench_hist(om, torch, bin_counts, g=None):
             forms.append(("_ranges", {"flags": om.CFG_HIST_RANGES}))
         if 40704 < bins <= 8388608:
             forms.append(("_partition", {"flags": om.CFG_HIST_PARTITION}))
+        if 40704 < bins <= 32 * 32768:
+            forms.append(("_tile_sort", {"flags": om.CFG_HIST_TILE_SORT}))
         for name, cfg in forms:
             h.zero_()
             om.histogram(k, bins, h, config=cfg)

@@ -11,7 +11,7 @@ import ctypes
 
 from . import _lib
 from ._lib import (ATOMIC_ADD, ATOMIC_CAS, ATOMIC_EXCHANGE, ATOMIC_INC, ATOMIC_MAX, BAND, BF16,
-                   BOR, BXOR, CFG_EXACT_THREAD_MAP, CFG_HIST_DIRECT, CFG_HIST_PARTITION, CFG_HIST_RANGES, CFG_HIST_TEAM_COPY, CFG_NO_MODEL, CFG_STATIC_TILES, F32, F64, I32, I64, LAND, LOR, MAX,
+                   BOR, BXOR, CFG_EXACT_THREAD_MAP, CFG_HIST_DIRECT, CFG_HIST_PARTITION, CFG_HIST_RANGES, CFG_HIST_TEAM_COPY, CFG_HIST_TILE_SORT, CFG_NO_MODEL, CFG_STATIC_TILES, F32, F64, I32, I64, LAND, LOR, MAX,
                    MIN, PROD, SUM, Config, MlpDims, OmprtError, Sched, Segment, check)
 
 __all__ = [
@@ -22,7 +22,7 @@ __all__ = [
     "model_features", "resolve_config", "tune_set", "workspace_reserve", "workspace_reset",
     "workspace_status", "finalize", "reduce_noalloc", "dtype_code", "OmprtError", "Config", "Sched", "Segment", "MlpDims",
     "I32", "I64", "F32", "F64", "BF16", "SUM", "MAX", "MIN", "PROD", "BAND", "BOR", "BXOR", "LAND",
-    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "CFG_HIST_DIRECT", "CFG_HIST_TEAM_COPY", "CFG_HIST_PARTITION", "CFG_HIST_RANGES", "CFG_EXACT_THREAD_MAP", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "region_axpy_sum", "udr_declare", "reduce_udr", "queue_chunk",
+    "LOR", "CFG_NO_MODEL", "CFG_STATIC_TILES", "CFG_HIST_DIRECT", "CFG_HIST_TEAM_COPY", "CFG_HIST_PARTITION", "CFG_HIST_RANGES", "CFG_HIST_TILE_SORT", "CFG_EXACT_THREAD_MAP", "reduce_array", "reduce_array_plan", "reduce_loc", "reduce_multi", "histogram", "generic_power", "region_axpy_sum", "udr_declare", "reduce_udr", "queue_chunk",
     "queue_map", "axpy_sum_queue",
 ]
 

@@ -23,6 +23,7 @@ CFG_HIST_DIRECT = 0x8
 CFG_EXACT_THREAD_MAP = 0x10
 CFG_HIST_PARTITION = 0x20
 CFG_HIST_RANGES = 0x40
+CFG_HIST_TILE_SORT = 0x80
 
 
 class Sched(ctypes.Structure):

@@ -542,6 +542,211 @@ __global__ void hist_part_merge_kernel(const uint32_t* __restrict__ partial, uin
     if (c) hist[b] += c;
 }
 
+// Tile-sorted partition, up to kTsortMaxRanges ranges: every tile of
+// kPartTile keys of a team's balanced block is ranked and sorted by range in
+// LDS as in the scatter above, but stored whole into a slot of its own,
+// kTsortSlot places: range r's run starts on a 16-byte boundary (each run is
+// padded with kTsortPad to a multiple of eight places) and the runs' starts,
+// in 16-byte vectors, go to tstart[g (R + 1) + r] (g = team x tiles per
+// team + tile; entry R is the slot's end).  No count pass and no scan
+// across teams: the range kernel then reads range r's run of every tile.
+// Key traffic: read once, places written once and read once (2 x the key
+// bytes), against three times for the partition above; the runs of a tile
+// are 8192 / R places long on average, long enough to stream for up to 32
+// ranges.
+constexpr uint32_t kTsortMaxRanges = 32;
+constexpr uint32_t kTsortSlot = kPartTile + 8 * kTsortMaxRanges;   // places, 16-byte multiple
+constexpr uint32_t kTsortPad = 0xFFFFu;                            // never a place (< kPartBins)
+static_assert(kTsortSlot % 8 == 0 && kTsortSlot / 8 < 65536, "slot of whole 16-byte vectors");
+
+__global__ __launch_bounds__(kPartThreads) void hist_tsort_scatter_kernel(
+    const int32_t* __restrict__ keys, int64_t n, uint32_t bins, uint32_t R, uint32_t NT,
+    uint16_t* __restrict__ part, uint16_t* __restrict__ tstart, uint32_t* status) {
+    const uint32_t C = part_copies(R);
+    __shared__ uint32_t tcnt[kTsortMaxRanges * kPartCopies];       // [range][copy]
+    __shared__ uint32_t toff[kTsortMaxRanges * kPartCopies + 1];   // exclusive scan of tcnt
+    __shared__ uint32_t pst[kTsortMaxRanges + 1];                  // padded run starts
+    __shared__ uint32_t wtot[kTsortMaxRanges * kPartCopies / kWave];
+    __shared__ __align__(16) uint16_t buf[kTsortSlot];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), P = blockDim.x;
+    const uint32_t copy = (uint32_t)tid % C;
+    const uint32_t RC = R * C;
+    if (tid == 0) s_bad = 0;
+    bool bad = false;
+    const Range blk = bal_share(n, gridDim.x, blockIdx.x);
+    // the next tile's keys are loaded while this one is sorted and stored
+    // (nothing reads them before then); positions past the block read as
+    // 0xFFFFFFFF (not a valid key)
+    uint32_t kn[kPartPerThread];
+    auto load_tile = [&](int64_t t0) {
+#pragma unroll
+        for (int q = 0; q < kPartPerThread; ++q) {
+            const int64_t i = t0 + (int64_t)q * P + tid;
+            kn[q] = i < blk.hi ? (uint32_t)__builtin_nontemporal_load(keys + i) : 0xFFFFFFFFu;
+        }
+    };
+    if (blk.lo < blk.hi) load_tile(blk.lo);
+    uint32_t j = 0;
+    for (int64_t t0 = blk.lo; t0 < blk.hi; t0 += kPartTile, ++j) {
+        for (uint32_t e = tid; e < RC; e += P) tcnt[e] = 0u;
+        uint32_t kr[kPartPerThread], rank[kPartPerThread];
+#pragma unroll
+        for (int q = 0; q < kPartPerThread; ++q) kr[q] = kn[q];
+        if (t0 + kPartTile < blk.hi) load_tile(t0 + kPartTile);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPartPerThread; ++q) {
+            if (kr[q] < bins)
+                rank[q] = __hip_atomic_fetch_add(tcnt + (kr[q] >> kPartLog2) * C + copy, 1u,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else if (t0 + (int64_t)q * P + tid < blk.hi)
+                bad = true;
+        }
+        __syncthreads();
+        // exclusive scan of the tile counts in (range, copy) order: entry e
+        // by thread e, the waves' totals through LDS
+        uint32_t v = 0, inc = 0;
+        if ((uint32_t)tid < RC) {
+            v = tcnt[tid];
+            inc = v;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t o = __shfl_up(inc, d, kWave);
+                if (lane >= d) inc += o;
+            }
+            if (lane == kWave - 1 || (uint32_t)tid == RC - 1) wtot[tid / kWave] = inc;
+        }
+        __syncthreads();
+        if ((uint32_t)tid < RC) {
+            uint32_t before = 0;
+            for (int w = 0; w < tid / kWave; ++w) before += wtot[w];
+            toff[tid] = before + inc - v;
+            if ((uint32_t)tid == RC - 1) toff[RC] = before + inc;
+        }
+        __syncthreads();
+        if (tid < kWave) {   // padded run starts: each run rounded up to eight places
+            const uint32_t r = (uint32_t)lane;
+            const uint32_t len = r < R ? toff[(r + 1) * C] - toff[r * C] : 0u;
+            const uint32_t pl = (len + 7u) & ~7u;
+            uint32_t inc = pl;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t o = __shfl_up(inc, d, kWave);
+                if (lane >= d) inc += o;
+            }
+            if (r <= R) pst[r] = inc - pl;   // entry R: the padded total
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPartPerThread; ++q)
+            if (kr[q] < bins) {
+                const uint32_t r = kr[q] >> kPartLog2;
+                buf[pst[r] + toff[r * C + copy] - toff[r * C] + rank[q]] =
+                    (uint16_t)(kr[q] & (kPartBins - 1));
+            }
+        if ((uint32_t)tid < R * 8) {   // the padding after each run
+            const uint32_t r = (uint32_t)tid / 8, u = (uint32_t)tid % 8;
+            const uint32_t at = pst[r] + (toff[(r + 1) * C] - toff[r * C]) + u;
+            if (at < pst[r + 1]) buf[at] = (uint16_t)kTsortPad;
+        }
+        __syncthreads();
+        const size_t g = (size_t)blockIdx.x * NT + j;
+        u32x4* __restrict__ slot = reinterpret_cast<u32x4*>(part + g * kTsortSlot);
+        const u32x4* lb = reinterpret_cast<const u32x4*>(buf);
+        for (uint32_t v = tid; v < pst[R] / 8; v += P) slot[v] = lb[v];
+        if ((uint32_t)tid <= R) tstart[g * (R + 1) + tid] = (uint16_t)(pst[tid] / 8);
+        // the next tile rewrites pst and buf only after two more barriers
+    }
+    for (uint32_t e = (uint32_t)tid; e < (NT - j) * (R + 1); e += P)   // empty tiles
+        tstart[((size_t)blockIdx.x * NT + j) * (R + 1) + e] = 0;
+    flag_bad(bad, &s_bad, status);
+}
+
+// Team (r, s): range r's runs in slice s of the G tile slots, each group of
+// SW lanes (a wave, or half of one when runs are short) sixteen tiles at a
+// time, one 16-byte vector of each in flight per lane (the LDS copy of the
+// range allows one team a CU, so registers are plentiful).  out is hist (S ==
+// 1) or the partials, S x bins.
+template <int SW>
+__global__ __launch_bounds__(kPartThreads) void hist_tsort_range_kernel(
+    const uint16_t* __restrict__ part, const uint16_t* __restrict__ tstart, int64_t G,
+    uint32_t R, uint32_t bins, uint32_t S, uint32_t* __restrict__ out) {
+    extern __shared__ __align__(16) char arena[];
+    lds_u32* h = (lds_u32*)arena;
+    const int tid = threadIdx.x, lane = tid & (SW - 1), P = blockDim.x;
+    const int64_t W = P / SW, wave = tid / SW;
+    const uint32_t r = blockIdx.x / S, s = blockIdx.x % S;
+    const uint32_t b0 = r << kPartLog2;
+    const uint32_t tb = bins - b0 < kPartBins ? bins - b0 : kPartBins;
+    for (uint32_t b = tid; b < tb; b += P) h[b] = 0u;
+    __syncthreads();
+    auto add = [&](uint32_t j) {
+        if (j != kTsortPad)
+            __hip_atomic_fetch_add(h + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    const Range sl = bal_share(G, S, s);
+    constexpr int K = 16;
+    const int64_t step = K * W;
+    // run starts and lengths of a group of K tiles (g0, g0 + W, ...): the next
+    // group's are loaded while this group's places stream in
+    // (lane k of the group loads tile k's entries; the group shares them)
+    static_assert(K <= SW, "a lane per tile of the group");
+    const int first = (tid & (kWave - 1)) - lane;   // the group's first lane in the wave
+    uint32_t st[K], nv[K];
+    auto fetch = [&](int64_t g0) {
+        const int64_t g = g0 + (int64_t)lane * W;
+        uint32_t a = 0, b = 0;
+        if (lane < K && g < sl.hi) {
+            a = tstart[g * (R + 1) + r];
+            b = tstart[g * (R + 1) + r + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            st[k] = (uint32_t)__shfl((int)a, first + k, kWave);
+            nv[k] = (uint32_t)__shfl((int)b, first + k, kWave) - st[k];
+        }
+    };
+    int64_t g0 = sl.lo + wave;
+    if (g0 < sl.hi) fetch(g0);
+    for (; g0 < sl.hi; g0 += step) {
+        uint32_t cst[K], cnv[K], mx = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            cst[k] = st[k];
+            cnv[k] = nv[k];
+            mx = cnv[k] > mx ? cnv[k] : mx;
+        }
+        if (g0 + step < sl.hi) fetch(g0 + step);
+        for (uint32_t i = lane; i < mx; i += SW) {
+            u32x4 w[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                w[k] = i < cnv[k] ? __builtin_nontemporal_load(
+                                        reinterpret_cast<const u32x4*>(part + (g0 + k * W) * kTsortSlot) +
+                                        cst[k] + i)
+                                  : u32x4{~0u, ~0u, ~0u, ~0u};
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    add(w[k][q] & 0xFFFFu);
+                    add(w[k][q] >> 16);
+                }
+        }
+    }
+    __syncthreads();
+    if (S == 1) {
+        for (uint32_t b = tid; b < tb; b += P) {
+            const uint32_t c = h[b];
+            if (c) out[b0 + b] += c;
+        }
+    } else {
+        uint32_t* o = out + (size_t)s * bins + b0;
+        for (uint32_t b = tid; b < tb; b += P) o[b] = h[b];
+    }
+}
+
 // Global pool of the team copies that do not fit LDS: per (device, stream),
 // grown on demand outside capture.
 struct Pool {
@@ -609,6 +814,10 @@ constexpr uint32_t kMaxBinTiles = 32;
 // costs; at 2^28 uniform keys 3 ranges ran at 441 G keys/s against 267 for
 // the partition, 7 ranges at 197 against 319.
 constexpr uint32_t kDefaultMaxBinTiles = 4;
+// LDS ranges the default takes before the tile sort (which reads the keys
+// once and moves 2-byte places twice): at 2^28 uniform keys 3 ranges ran at
+// 444 G keys/s against 535 for the tile sort, 2 ranges at 793 against 432.
+constexpr uint32_t kDefaultMaxTsortTiles = 2;
 
 // Partitioned bins (count, scan, scatter, range, merge), teams x 512
 // threads for the passes over the keys.
@@ -665,6 +874,62 @@ static omprt_status histogram_partitioned(const int32_t* d_keys, int64_t n, uint
     return OMPRT_OK;
 }
 
+// Tile-sorted bins (scatter into tile slots, range, merge), up to
+// kTsortMaxRanges ranges; teams x 512 threads for the pass over the keys.
+static omprt_status histogram_tsorted(const int32_t* d_keys, int64_t n, uint32_t bins,
+                                      int32_t* d_hist, int teams, hipStream_t stream) {
+    const uint32_t R = (bins + kPartBins - 1) >> kPartLog2;
+    if (R > kTsortMaxRanges)
+        return fail(OMPRT_ERR_INVALID, "tile-sorted histogram: %u bins above %u", bins,
+                    kTsortMaxRanges * kPartBins);
+    const uint32_t T = (uint32_t)teams;
+    const int64_t per_team = (n + T - 1) / T;
+    const uint32_t NT = (uint32_t)std::max<int64_t>(1, (per_team + kPartTile - 1) / kPartTile);
+    const int64_t G = (int64_t)T * NT;
+    uint32_t S = (uint32_t)((2 * device_cus() + R - 1) / R);
+    S = std::min<uint32_t>(std::max<uint32_t>(S, 1u), 64u);
+    auto up = [](uint64_t b) { return (b + 255) / 256 * 256; };
+    const uint64_t b_part = up((uint64_t)G * kTsortSlot * 2),
+                   b_ts = up((uint64_t)G * (R + 1) * 2),
+                   b_partial = S > 1 ? up((uint64_t)S * bins * 4) : 0;
+    void* pool = nullptr;
+    if (omprt_status st = pool_get(stream, b_part + b_ts + b_partial, &pool)) return st;
+    char* p = static_cast<char*>(pool);
+    uint16_t* part = reinterpret_cast<uint16_t*>(p);
+    uint16_t* tstart = reinterpret_cast<uint16_t*>(p + b_part);
+    uint32_t* partial = reinterpret_cast<uint32_t*>(p + b_part + b_ts);
+    Workspace* ws = nullptr;
+    if (omprt_status st = workspace_get(stream, 1, &ws)) return st;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(d_hist);
+    hipLaunchKernelGGL(hist_tsort_scatter_kernel, dim3(T), dim3(kPartThreads), 0, stream, d_keys,
+                       n, bins, R, NT, part, tstart, ws->status());
+    // runs average kPartTile / R places: from 16 ranges on (64 vectors or
+    // fewer) half a wave takes a tile
+    const void* range_kernel = R >= 16 ? reinterpret_cast<const void*>(hist_tsort_range_kernel<32>)
+                                       : reinterpret_cast<const void*>(hist_tsort_range_kernel<64>);
+    const uint32_t lds = std::min(bins, kPartBins) * 4;
+    if (lds > 64 * 1024) {   // past the default dynamic LDS limit: ask for it
+        const hipError_t e =
+            hipFuncSetAttribute(range_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return fail(OMPRT_ERR_DEVICE, "histogram: %u bytes of LDS: %s", lds,
+                        hipGetErrorString(e));
+    }
+    uint32_t* dst = S > 1 ? partial : hist;
+    if (R >= 16)
+        hipLaunchKernelGGL(hist_tsort_range_kernel<32>, dim3(R * S), dim3(kPartThreads), lds,
+                           stream, part, tstart, G, R, bins, S, dst);
+    else
+        hipLaunchKernelGGL(hist_tsort_range_kernel<64>, dim3(R * S), dim3(kPartThreads), lds,
+                           stream, part, tstart, G, R, bins, S, dst);
+    if (S > 1)
+        hipLaunchKernelGGL(hist_part_merge_kernel, dim3((bins + 255) / 256), dim3(256), 0, stream,
+                           partial, S, bins, hist);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "histogram launch: %s", hipGetErrorString(e));
+    return OMPRT_OK;
+}
+
 }  // namespace omprt
 
 using namespace omprt;
@@ -694,28 +959,38 @@ extern "C" omprt_status omprt_histogram(const int32_t* d_keys, int64_t n, int32_
     }
     const uint32_t flags = cfg ? cfg->flags : 0u;
     const uint32_t forced = flags & (OMPRT_CFG_HIST_DIRECT | OMPRT_CFG_HIST_TEAM_COPY |
-                                     OMPRT_CFG_HIST_PARTITION | OMPRT_CFG_HIST_RANGES);
+                                     OMPRT_CFG_HIST_PARTITION | OMPRT_CFG_HIST_RANGES |
+                                     OMPRT_CFG_HIST_TILE_SORT);
     if (forced & (forced - 1))
-        return fail(OMPRT_ERR_INVALID,
-                    "at most one of HIST_DIRECT, HIST_TEAM_COPY, HIST_PARTITION, HIST_RANGES");
+        return fail(OMPRT_ERR_INVALID, "at most one of HIST_DIRECT, HIST_TEAM_COPY, "
+                                       "HIST_PARTITION, HIST_RANGES, HIST_TILE_SORT");
     if ((flags & OMPRT_CFG_HIST_PARTITION) && bins > (int64_t)kPartMaxRanges * kPartBins)
         return fail(OMPRT_ERR_INVALID, "HIST_PARTITION takes up to %u bins",
                     kPartMaxRanges * kPartBins);
+    if ((flags & OMPRT_CFG_HIST_TILE_SORT) && bins > (int64_t)kTsortMaxRanges * kPartBins)
+        return fail(OMPRT_ERR_INVALID, "HIST_TILE_SORT takes up to %u bins",
+                    kTsortMaxRanges * kPartBins);
     if (n == 0) return OMPRT_OK;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     // Bins that do not fit one team's LDS: up to four ranges of bins, each
     // counted by its own teams (every team reads its block of the keys and
     // counts those in its range); from five ranges on, the keys partitioned by
-    // range first (read twice, 16-bit places written and read once), up to
-    // kPartMaxRanges x kPartBins bins (and 16 GiB of places); past that,
+    // range first: up to kTsortMaxRanges ranges each tile sorted by range into
+    // a slot of its own (keys read once, 16-bit places written and read
+    // once), then up to kPartMaxRanges x kPartBins bins partitioned across
+    // teams (keys read twice), both within 16 GiB of places; past that,
     // atomics on hist.  On request: ranges up to kMaxBinTiles of them, team
-    // copies in the global pool (atomics at L2, then a merge), partitioning,
-    // or atomics on hist for any bin count.
+    // copies in the global pool (atomics at L2, then a merge), either
+    // partition, or atomics on hist for any bin count.
     const uint32_t lds_bins = hist_lds_cap() / 4 / 4 * 4;
     uint32_t tiles = (uint32_t)((bins + lds_bins - 1) / lds_bins);
     uint32_t tile_bins = tiles > 1 ? (uint32_t)((bins + tiles - 1) / tiles + 3) / 4 * 4 : (uint32_t)bins;
     const bool part_fits = bins <= (int64_t)kPartMaxRanges * kPartBins &&
                            (uint64_t)n * 2 <= ((uint64_t)16 << 30);
+    const bool tsort_fits = part_fits && bins <= (int64_t)kTsortMaxRanges * kPartBins;
+    if ((flags & OMPRT_CFG_HIST_TILE_SORT) ||
+        (!forced && tiles > kDefaultMaxTsortTiles && tsort_fits))
+        return histogram_tsorted(d_keys, n, (uint32_t)bins, d_hist, teams, stream);
     if ((flags & OMPRT_CFG_HIST_PARTITION) ||
         (!forced && tiles > kDefaultMaxBinTiles && part_fits))
         return histogram_partitioned(d_keys, n, (uint32_t)bins, d_hist, teams, stream);

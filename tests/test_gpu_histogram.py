@@ -42,7 +42,8 @@ def test_uniform_keys(gpu_lib, bins):
         assert np.array_equal(run(gpu_lib, keys, bins, h0), want)
 
 
-@pytest.mark.parametrize("flag", ["HIST_TEAM_COPY", "HIST_DIRECT", "HIST_PARTITION", "HIST_RANGES"])
+@pytest.mark.parametrize("flag", ["HIST_TEAM_COPY", "HIST_DIRECT", "HIST_PARTITION", "HIST_RANGES",
+                                  "HIST_TILE_SORT"])
 @pytest.mark.parametrize("bins", [7, 16257, 32769, 1 << 20, 1400000])
 def test_forced_strategies(gpu_lib, flag, bins):
     """Team copies from the global pool (team-shared allocation falling back past LDS) and
@@ -52,6 +53,10 @@ def test_forced_strategies(gpu_lib, flag, bins):
     cfg = {"flags": getattr(gpu_lib, "CFG_" + flag)}
     if flag == "HIST_TEAM_COPY":
         cfg["teams"] = 16
+    if flag == "HIST_TILE_SORT" and bins > 32 * 32768:   # 32 ranges at most: refused
+        with pytest.raises(gpu_lib.OmprtError):
+            run(gpu_lib, np.zeros(10, dtype=np.int32), bins, np.zeros(bins), cfg)
+        return
     for n in (1, 1000, 300001):
         keys = g.integers(0, bins, n).astype(np.int32)
         h0 = g.integers(-1000, 1000, bins).astype(np.int32)
@@ -94,7 +99,7 @@ def test_out_of_range_keys_flagged(gpu_lib):
         om.workspace_reset()
     assert om.workspace_status(stream=s) == 0
     # the atomic and the partitioned strategies flag them the same way
-    for flag in (om.CFG_HIST_DIRECT, om.CFG_HIST_PARTITION):
+    for flag in (om.CFG_HIST_DIRECT, om.CFG_HIST_PARTITION, om.CFG_HIST_TILE_SORT):
         with torch.cuda.stream(s):
             h.zero_()
             om.histogram(k, 100, h, config={"flags": flag})
@@ -151,14 +156,17 @@ def test_partition_at_scale(gpu_lib, bins, skew):
     assert np.array_equal(run(gpu_lib, keys, bins, h0), want), (bins, skew)
 
 
-@pytest.mark.parametrize("teams", [1, 7, 100, 1500, 2500])
-def test_partition_team_counts(gpu_lib, teams):
-    """The forced partition with team counts that are not whole waves of the per-range scan (1,
-    7, 100), and with more teams than one scan workgroup covers in one piece (1500, 2500: the
-    range's counts are scanned 1024 at a time with a carry), over 5 and 40 ranges."""
+@pytest.mark.parametrize("flag,teams", [("HIST_PARTITION", t) for t in (1, 7, 100, 1500, 2500)] +
+                         [("HIST_TILE_SORT", t) for t in (1, 7, 100, 1500, 2500)])
+def test_partition_team_counts(gpu_lib, flag, teams):
+    """The forced partitions with team counts that are not whole waves of the per-range scan
+    (1, 7, 100), and with more teams than one scan workgroup covers in one piece (1500, 2500:
+    the range's counts are scanned 1024 at a time with a carry); for the tile sort, teams
+    with several tiles, one partial tile, or none (2500 teams over 4097 keys), over 5 and
+    32 or 40 ranges."""
     g = np.random.Generator(np.random.PCG64(teams))
-    cfg = {"flags": gpu_lib.CFG_HIST_PARTITION, "teams": teams}
-    for bins in (5 * 32768 - 3, 1302529):
+    cfg = {"flags": getattr(gpu_lib, "CFG_" + flag), "teams": teams}
+    for bins in (5 * 32768 - 3, 1302529 if flag == "HIST_PARTITION" else 1048576):
         for n in (1, 4097, 1000003):
             keys = g.integers(0, bins, n).astype(np.int32)
             h0 = g.integers(-1000, 1000, bins).astype(np.int32)
