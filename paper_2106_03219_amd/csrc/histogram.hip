@@ -552,9 +552,9 @@ __global__ void hist_part_merge_kernel(const uint32_t* __restrict__ partial, uin
 // across teams: the range kernel then reads range r's run of every tile.
 // Key traffic: read once, places written once and read once (2 x the key
 // bytes), against three times for the partition above; the runs of a tile
-// are 8192 / R places long on average, long enough to stream for up to 32
-// ranges.
-constexpr uint32_t kTsortMaxRanges = 32;
+// are 8192 / R places long on average (128 at 64 ranges), and the padding
+// adds at most 8 R places a tile (6 % at 64 ranges).
+constexpr uint32_t kTsortMaxRanges = 64;
 constexpr uint32_t kTsortSlot = kPartTile + 8 * kTsortMaxRanges;   // places, 16-byte multiple
 constexpr uint32_t kTsortPad = 0xFFFFu;                            // never a place (< kPartBins)
 static_assert(kTsortSlot % 8 == 0 && kTsortSlot / 8 < 65536, "slot of whole 16-byte vectors");
@@ -626,16 +626,20 @@ __global__ __launch_bounds__(kPartThreads) void hist_tsort_scatter_kernel(
         }
         __syncthreads();
         if (tid < kWave) {   // padded run starts: each run rounded up to eight places
-            const uint32_t r = (uint32_t)lane;
-            const uint32_t len = r < R ? toff[(r + 1) * C] - toff[r * C] : 0u;
-            const uint32_t pl = (len + 7u) & ~7u;
-            uint32_t inc = pl;
+            uint32_t carry = 0;
+            for (uint32_t r0 = 0; r0 <= R; r0 += kWave) {
+                const uint32_t r = r0 + (uint32_t)lane;
+                const uint32_t len = r < R ? toff[(r + 1) * C] - toff[r * C] : 0u;
+                const uint32_t pl = (len + 7u) & ~7u;
+                uint32_t inc = pl;
 #pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const uint32_t o = __shfl_up(inc, d, kWave);
-                if (lane >= d) inc += o;
+                for (int d = 1; d < kWave; d <<= 1) {
+                    const uint32_t o = __shfl_up(inc, d, kWave);
+                    if (lane >= d) inc += o;
+                }
+                if (r <= R) pst[r] = carry + inc - pl;   // entry R: the padded total
+                carry += __shfl(inc, kWave - 1, kWave);
             }
-            if (r <= R) pst[r] = inc - pl;   // entry R: the padded total
         }
         __syncthreads();
 #pragma unroll
@@ -904,9 +908,11 @@ static omprt_status histogram_tsorted(const int32_t* d_keys, int64_t n, uint32_t
     hipLaunchKernelGGL(hist_tsort_scatter_kernel, dim3(T), dim3(kPartThreads), 0, stream, d_keys,
                        n, bins, R, NT, part, tstart, ws->status());
     // runs average kPartTile / R places: from 16 ranges on (64 vectors or
-    // fewer) half a wave takes a tile
-    const void* range_kernel = R >= 16 ? reinterpret_cast<const void*>(hist_tsort_range_kernel<32>)
-                                       : reinterpret_cast<const void*>(hist_tsort_range_kernel<64>);
+    // fewer) half a wave takes a tile, from 48 on a quarter
+    const void* range_kernel =
+        R >= 48   ? reinterpret_cast<const void*>(hist_tsort_range_kernel<16>)
+        : R >= 16 ? reinterpret_cast<const void*>(hist_tsort_range_kernel<32>)
+                  : reinterpret_cast<const void*>(hist_tsort_range_kernel<64>);
     const uint32_t lds = std::min(bins, kPartBins) * 4;
     if (lds > 64 * 1024) {   // past the default dynamic LDS limit: ask for it
         const hipError_t e =
@@ -916,7 +922,10 @@ static omprt_status histogram_tsorted(const int32_t* d_keys, int64_t n, uint32_t
                         hipGetErrorString(e));
     }
     uint32_t* dst = S > 1 ? partial : hist;
-    if (R >= 16)
+    if (R >= 48)
+        hipLaunchKernelGGL(hist_tsort_range_kernel<16>, dim3(R * S), dim3(kPartThreads), lds,
+                           stream, part, tstart, G, R, bins, S, dst);
+    else if (R >= 16)
         hipLaunchKernelGGL(hist_tsort_range_kernel<32>, dim3(R * S), dim3(kPartThreads), lds,
                            stream, part, tstart, G, R, bins, S, dst);
     else
