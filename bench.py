@@ -507,7 +507,8 @@ def bench_udr(om, torch):
 def bench_queue(om, torch, leg=None):
     """The AXPY + sum body over 2^26 fp32 under schedule(dynamic, c) and schedule(guided,
     c) for the threads of each team (distribute static, one team per compute unit, 512
-    threads), next to the static schedule with the same chunk.  y must be bit-identical to
+    threads, and the runtime's default team size), next to the static schedule with the
+    same chunk.  y must be bit-identical to
     the static schedule's and the sums within 2e-6 of it."""
     import synth
     _log("AXPY 2^26 under dynamic / guided schedules")
@@ -541,6 +542,16 @@ def bench_queue(om, torch, leg=None):
             rels[f"{kind},c={c}"] = rel
         us = _time_us(fn, torch)
         out[f"{kind},c={c}"] = round(12 * n / us / 1e3, 1)
+        if kind != "static":   # the runtime's own team size (threads 0)
+            fd = lambda: om.axpy_sum_queue(kind, 0.7, x, y, s, 0, 0, 0, c)
+            y.copy_(y0)
+            s.zero_()
+            fd()
+            torch.cuda.synchronize()
+            agree &= bool(torch.equal(y, yref))
+            agree &= abs(s.item() - sref.item()) <= 2e-6 * abs(sref.item())
+            us = _time_us(fd, torch)
+            out[f"{kind},c={c},default_threads"] = round(12 * n / us / 1e3, 1)
     res = {"n": n, "bytes_per_iter": 12, "gb_s": out, "y_and_sum_agree_with_static": agree}
     if rels:
         res["sum_rel_err_vs_oracle"] = rels

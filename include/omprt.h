@@ -554,9 +554,11 @@ omprt_status omprt_queue_map(const omprt_sched *s, int32_t kind,
 /*
  * omprt_axpy_sum's body and sum (y[i] <- fmaf(a, x[i], y[i]); *d_sum +=
  * sum of the updated y, compensated fp32) under kind instead of a static
- * for-schedule.  s->num_teams / threads_per_team of 0: one team per compute
- * unit / 512 threads (at most 512).  Dynamic chunks of one iteration are taken four per
- * request.  Guided tables as for omprt_queue_map.  y is bit-identical to the static schedules' result; the sum may
+ * for-schedule.  s->num_teams of 0: one team per compute unit;
+ * threads_per_team of 0: 512 for dynamic chunks under 16 iterations, else
+ * 256 (at most 512; a guided schedule's chunk sizes follow the team size).
+ * Dynamic chunks of one iteration are taken four per request.  Guided tables
+ * as for omprt_queue_map.  y is bit-identical to the static schedules' result; the sum may
  * differ in its last bits (the order of accumulation depends on which
  * thread ran which chunk).
  */
