@@ -207,7 +207,8 @@ extern "C" omprt_status omprt_region_axpy_sum(float a, const float* d_x, float* 
         if (xb < yb + s->n * 4 && yb < xb + s->n * 4) return fail(OMPRT_ERR_INVALID, "x and y overlap");
     }
     LaunchCfg lc;
-    if (omprt_status st = resolve_config(s->n, OMPRT_F32, OMPRT_SUM, 1, s->chunk, cfg, &lc, nullptr))
+    // body 2: the AXPY-then-sum region (the AXPY body's model features, its own heuristic)
+    if (omprt_status st = resolve_config(s->n, OMPRT_F32, OMPRT_SUM, 2, s->chunk, cfg, &lc, nullptr))
         return st;
     const int teams = s->num_teams ? s->num_teams : lc.teams;
     if (teams > 65535)

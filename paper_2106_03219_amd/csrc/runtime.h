@@ -55,7 +55,9 @@ struct LaunchCfg {
 enum ConfigSource { kSrcExplicit = 0, kSrcModel = 1, kSrcTuned = 2, kSrcHeuristic = 3 };
 
 // Explicit fields of cfg win; the rest come from the learned model, else the
-// tuned cache, else the heuristic.  body: 0 reduction, 1 AXPY.
+// tuned cache, else the heuristic.  body: 0 reduction, 1 AXPY, 2 the
+// AXPY-then-sum region (the AXPY's model features and tuned entries, a
+// heuristic of its own).
 omprt_status resolve_config(int64_t n, int dtype, int op, int body, int64_t chunk,
                             const omprt_config* cfg, LaunchCfg* out, int* source);
 
