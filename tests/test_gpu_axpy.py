@@ -39,7 +39,12 @@ SMALL = [(1, 1, 1, 0, 0), (100, 2, 64, 0, 0), (1000, 3, 9, 0, 1), (1000, 3, 9, 1
          # line), dist_schedule blocks, a final partial round of chunks
          (300000, 7, 256, 0, 0), (300000, 7, 512, 0, 100), ((1 << 20), 4, 128, 0, 0),
          ((1 << 20) + 37, 3, 192, 5000, 64), (1000, 2, 256, 0, 0), (70000, 1, 512, 0, 2048),
-         ((1 << 20) + 5, 9, 448, 0, 96), (200000, 33, 64, 0, 0)]
+         ((1 << 20) + 5, 9, 448, 0, 96), (200000, 33, 64, 0, 0),
+         # the runtime's own launch for the chunk sizes it treats apart (chunk 1:
+         # one team of 512 per compute unit; 1024 and more: 512 threads, ~128
+         # chunks a team), ragged sizes
+         (100003, 0, 0, 0, 1), (300001, 0, 0, 0, 1024), (1000003, 0, 0, 0, 4096),
+         (70000, 0, 0, 0, 4096)]
 
 
 @pytest.mark.parametrize("n,T,P,dc,c", SMALL)

@@ -38,7 +38,9 @@ SCHEDS = [(1, 1, 1, 0), (100, 2, 64, 0), (1000, 3, 9, 0), (1000, 3, 9, 13), (409
           (5, 8, 64, 0), (300001, 7, 1000, 0),
           # whole-wave teams with lane runs of one line or more (through LDS
           # lines): aligned and ragged runs, distribute blocks
-          ((1 << 20) + 3, 4, 256, 0), (300000, 7, 512, 0), ((1 << 20) + 37, 3, 192, 5000)]
+          ((1 << 20) + 3, 4, 256, 0), (300000, 7, 512, 0), ((1 << 20) + 37, 3, 192, 5000),
+          # the runtime's own launch (its chunk-dependent choices) at a larger size
+          ((1 << 21) + 11, 0, 0, 0)]
 
 
 @pytest.mark.parametrize("n,T,P,dc", SCHEDS)
