@@ -886,7 +886,8 @@ static omprt_status histogram_tsorted(const int32_t* d_keys, int64_t n, uint32_t
     if (R > kTsortMaxRanges)
         return fail(OMPRT_ERR_INVALID, "tile-sorted histogram: %u bins above %u", bins,
                     kTsortMaxRanges * kPartBins);
-    const uint32_t T = (uint32_t)teams;
+    // no more teams than tiles: a team without keys would still own a slot
+    const uint32_t T = (uint32_t)std::min<int64_t>(teams, (n + kPartTile - 1) / kPartTile);
     const int64_t per_team = (n + T - 1) / T;
     const uint32_t NT = (uint32_t)std::max<int64_t>(1, (per_team + kPartTile - 1) / kPartTile);
     const int64_t G = (int64_t)T * NT;

@@ -161,9 +161,9 @@ def test_partition_at_scale(gpu_lib, bins, skew):
 def test_partition_team_counts(gpu_lib, flag, teams):
     """The forced partitions with team counts that are not whole waves of the per-range scan
     (1, 7, 100), and with more teams than one scan workgroup covers in one piece (1500, 2500:
-    the range's counts are scanned 1024 at a time with a carry); for the tile sort, teams
-    with several tiles, one partial tile, or none (2500 teams over 4097 keys), over 5, 40 and
-    the most ranges each takes (64, 256)."""
+    the range's counts are scanned 1024 at a time with a carry); for the tile sort (which
+    takes no more teams than tiles), teams with several tiles or one partial tile, over 5, 40
+    and the most ranges each takes (64, 256)."""
     g = np.random.Generator(np.random.PCG64(teams))
     cfg = {"flags": getattr(gpu_lib, "CFG_" + flag), "teams": teams}
     for bins in (5 * 32768 - 3, 1302529, 2097152 if flag == "HIST_TILE_SORT" else 8388608):
@@ -172,3 +172,15 @@ def test_partition_team_counts(gpu_lib, flag, teams):
             h0 = g.integers(-1000, 1000, bins).astype(np.int32)
             want, _ = oracle.histogram(keys, bins, hist=h0)
             assert np.array_equal(run(gpu_lib, keys, bins, h0, cfg), want), (teams, bins, n)
+
+
+def test_tile_sort_team_with_fewer_tiles(gpu_lib):
+    """49 153 keys over 3 teams: the first team's block is 16 385 keys (three tiles), the
+    others 16 384 (two), so their third tile's run starts are written empty."""
+    g = np.random.Generator(np.random.PCG64(31))
+    cfg = {"flags": gpu_lib.CFG_HIST_TILE_SORT, "teams": 3}
+    for bins in (100000, 2097152):
+        keys = g.integers(0, bins, 49153).astype(np.int32)
+        h0 = g.integers(-1000, 1000, bins).astype(np.int32)
+        want, _ = oracle.histogram(keys, bins, hist=h0)
+        assert np.array_equal(run(gpu_lib, keys, bins, h0, cfg), want), bins
