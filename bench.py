@@ -341,7 +341,7 @@ def bench_hist(om, torch, bin_counts, g=None):
     """Histograms of 2^28 uniform int32 keys: the default strategy, atomics on hist
     (HIST_DIRECT) and, where they apply, range-by-range LDS copies (HIST_RANGES, up to 32
     ranges of 40 704 bins), the partition by bin range across teams (HIST_PARTITION, up to
-    8 388 608 bins) and the per-tile sort by bin range (HIST_TILE_SORT, up to 2 097 152 bins),
+    8 388 608 bins) and the per-tile sort by bin range (HIST_TILE_SORT, up to 4 194 304 bins),
     each checked against torch.bincount."""
     n = 1 << 28
     if g is None:
@@ -357,7 +357,7 @@ def bench_hist(om, torch, bin_counts, g=None):
             forms.append(("_ranges", {"flags": om.CFG_HIST_RANGES}))
         if 40704 < bins <= 8388608:
             forms.append(("_partition", {"flags": om.CFG_HIST_PARTITION}))
-        if 40704 < bins <= 64 * 32768:
+        if 40704 < bins <= 128 * 32768:
             forms.append(("_tile_sort", {"flags": om.CFG_HIST_TILE_SORT}))
         for name, cfg in forms:
             h.zero_()
@@ -1012,7 +1012,7 @@ def run(args, om, torch):
 
     if args.only_hist:
         bins = (256, 4096, 16257, 40704, 40705, 81409, 100000, 260096, 1 << 20, 1302529, 1 << 21,
-                1 << 23, 1 << 24)
+                1 << 22, 1 << 23, 1 << 24)
         print(json.dumps({"histogram": bench_hist(om, torch, bins)}), flush=True)
         return
 

@@ -131,7 +131,7 @@ typedef struct {
 #define OMPRT_CFG_HIST_TILE_SORT 0x80u  /* histogram: sort each tile of keys by
                                           bin range into a slot of its own,
                                           then count each range's runs in LDS
-                                          (up to 2 097 152 bins) */
+                                          (up to 4 194 304 bins) */
 #define OMPRT_CFG_EXACT_THREAD_MAP 0x10u /* omprt_reduce (sum / max / min): every
                                             thread reduces exactly its
                                             schedule(static) run of the team's
@@ -249,13 +249,13 @@ omprt_status omprt_reduce(const void *d_in, int64_t n, int32_t dtype,
  * past that the keys are first partitioned by bin range (ranges of 32 768
  * bins) into a buffer of the library's pool of 16-bit places within their
  * range, then each range's places are counted in an LDS copy of that range:
- * up to 2 097 152 bins every tile of 8192 keys is sorted by range into a
+ * up to 4 194 304 bins every tile of 8192 keys is sorted by range into a
  * slot of its own (the keys read once); up to 8 388 608 bins the ranges are
  * laid out across teams (counts per range and team, a prefix sum, then the
  * scatter: the keys read twice); beyond, every key is an atomic add on
  * d_hist itself (no copy).  cfg->flags:
  * OMPRT_CFG_HIST_RANGES counts range by range up to 32 ranges;
- * OMPRT_CFG_HIST_TILE_SORT sorts tiles for any bin count up to 2 097 152;
+ * OMPRT_CFG_HIST_TILE_SORT sorts tiles for any bin count up to 4 194 304;
  * OMPRT_CFG_HIST_PARTITION partitions across teams for any bin count up to
  * 8 388 608;
  * OMPRT_CFG_HIST_TEAM_COPY keeps team copies past the ranges, each a slice

@@ -552,9 +552,9 @@ __global__ void hist_part_merge_kernel(const uint32_t* __restrict__ partial, uin
 // across teams: the range kernel then reads range r's run of every tile.
 // Key traffic: read once, places written once and read once (2 x the key
 // bytes), against three times for the partition above; the runs of a tile
-// are 8192 / R places long on average (128 at 64 ranges), and the padding
-// adds at most 8 R places a tile (6 % at 64 ranges).
-constexpr uint32_t kTsortMaxRanges = 64;
+// are 8192 / R places long on average (64 at 128 ranges), and the padding
+// adds at most 8 R places a tile (12.5 % at 128 ranges).
+constexpr uint32_t kTsortMaxRanges = 128;
 constexpr uint32_t kTsortSlot = kPartTile + 8 * kTsortMaxRanges;   // places, 16-byte multiple
 constexpr uint32_t kTsortPad = 0xFFFFu;                            // never a place (< kPartBins)
 static_assert(kTsortSlot % 8 == 0 && kTsortSlot / 8 < 65536, "slot of whole 16-byte vectors");
@@ -649,8 +649,8 @@ __global__ __launch_bounds__(kPartThreads) void hist_tsort_scatter_kernel(
                 buf[pst[r] + toff[r * C + copy] - toff[r * C] + rank[q]] =
                     (uint16_t)(kr[q] & (kPartBins - 1));
             }
-        if ((uint32_t)tid < R * 8) {   // the padding after each run
-            const uint32_t r = (uint32_t)tid / 8, u = (uint32_t)tid % 8;
+        for (uint32_t e = (uint32_t)tid; e < R * 8; e += P) {   // the padding after each run
+            const uint32_t r = e / 8, u = e % 8;
             const uint32_t at = pst[r] + (toff[(r + 1) * C] - toff[r * C]) + u;
             if (at < pst[r + 1]) buf[at] = (uint16_t)kTsortPad;
         }
@@ -690,7 +690,7 @@ __global__ __launch_bounds__(kPartThreads) void hist_tsort_range_kernel(
             __hip_atomic_fetch_add(h + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     const Range sl = bal_share(G, S, s);
-    constexpr int K = 16;
+    constexpr int K = SW < 16 ? SW : 16;   // tiles of a group: one lane fetches each
     const int64_t step = K * W;
     // run starts and lengths of a group of K tiles (g0, g0 + W, ...): the next
     // group's are loaded while this group's places stream in
@@ -909,9 +909,10 @@ static omprt_status histogram_tsorted(const int32_t* d_keys, int64_t n, uint32_t
     hipLaunchKernelGGL(hist_tsort_scatter_kernel, dim3(T), dim3(kPartThreads), 0, stream, d_keys,
                        n, bins, R, NT, part, tstart, ws->status());
     // runs average kPartTile / R places: from 16 ranges on (64 vectors or
-    // fewer) half a wave takes a tile, from 48 on a quarter
+    // fewer) half a wave takes a tile, from 48 on a quarter, from 96 an eighth
     const void* range_kernel =
-        R >= 48   ? reinterpret_cast<const void*>(hist_tsort_range_kernel<16>)
+        R >= 96   ? reinterpret_cast<const void*>(hist_tsort_range_kernel<8>)
+        : R >= 48 ? reinterpret_cast<const void*>(hist_tsort_range_kernel<16>)
         : R >= 16 ? reinterpret_cast<const void*>(hist_tsort_range_kernel<32>)
                   : reinterpret_cast<const void*>(hist_tsort_range_kernel<64>);
     const uint32_t lds = std::min(bins, kPartBins) * 4;
@@ -923,7 +924,10 @@ static omprt_status histogram_tsorted(const int32_t* d_keys, int64_t n, uint32_t
                         hipGetErrorString(e));
     }
     uint32_t* dst = S > 1 ? partial : hist;
-    if (R >= 48)
+    if (R >= 96)
+        hipLaunchKernelGGL(hist_tsort_range_kernel<8>, dim3(R * S), dim3(kPartThreads), lds,
+                           stream, part, tstart, G, R, bins, S, dst);
+    else if (R >= 48)
         hipLaunchKernelGGL(hist_tsort_range_kernel<16>, dim3(R * S), dim3(kPartThreads), lds,
                            stream, part, tstart, G, R, bins, S, dst);
     else if (R >= 16)

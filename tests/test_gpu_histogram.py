@@ -44,7 +44,7 @@ def test_uniform_keys(gpu_lib, bins):
 
 @pytest.mark.parametrize("flag", ["HIST_TEAM_COPY", "HIST_DIRECT", "HIST_PARTITION", "HIST_RANGES",
                                   "HIST_TILE_SORT"])
-@pytest.mark.parametrize("bins", [7, 16257, 32769, 1 << 20, 1400000, 2097152, 2097153])
+@pytest.mark.parametrize("bins", [7, 16257, 32769, 1 << 20, 1400000, 2097153, 4194304, 4194305])
 def test_forced_strategies(gpu_lib, flag, bins):
     """Team copies from the global pool (team-shared allocation falling back past LDS) and
     atomics on hist, each forced where the default would choose otherwise (the pool holds a
@@ -53,7 +53,7 @@ def test_forced_strategies(gpu_lib, flag, bins):
     cfg = {"flags": getattr(gpu_lib, "CFG_" + flag)}
     if flag == "HIST_TEAM_COPY":
         cfg["teams"] = 16
-    if flag == "HIST_TILE_SORT" and bins > 64 * 32768:   # 64 ranges at most: refused
+    if flag == "HIST_TILE_SORT" and bins > 128 * 32768:   # 128 ranges at most: refused
         with pytest.raises(gpu_lib.OmprtError):
             run(gpu_lib, np.zeros(10, dtype=np.int32), bins, np.zeros(bins), cfg)
         return
@@ -163,10 +163,10 @@ def test_partition_team_counts(gpu_lib, flag, teams):
     (1, 7, 100), and with more teams than one scan workgroup covers in one piece (1500, 2500:
     the range's counts are scanned 1024 at a time with a carry); for the tile sort (which
     takes no more teams than tiles), teams with several tiles or one partial tile, over 5, 40
-    and the most ranges each takes (64, 256)."""
+    and the most ranges each takes (128, 256)."""
     g = np.random.Generator(np.random.PCG64(teams))
     cfg = {"flags": getattr(gpu_lib, "CFG_" + flag), "teams": teams}
-    for bins in (5 * 32768 - 3, 1302529, 2097152 if flag == "HIST_TILE_SORT" else 8388608):
+    for bins in (5 * 32768 - 3, 1302529, 4194304 if flag == "HIST_TILE_SORT" else 8388608):
         for n in (1, 4097, 1000003):
             keys = g.integers(0, bins, n).astype(np.int32)
             h0 = g.integers(-1000, 1000, bins).astype(np.int32)
@@ -179,7 +179,7 @@ def test_tile_sort_team_with_fewer_tiles(gpu_lib):
     others 16 384 (two), so their third tile's run starts are written empty."""
     g = np.random.Generator(np.random.PCG64(31))
     cfg = {"flags": gpu_lib.CFG_HIST_TILE_SORT, "teams": 3}
-    for bins in (100000, 2097152):
+    for bins in (100000, 2097152, 4194304):
         keys = g.integers(0, bins, 49153).astype(np.int32)
         h0 = g.integers(-1000, 1000, bins).astype(np.int32)
         want, _ = oracle.histogram(keys, bins, hist=h0)
