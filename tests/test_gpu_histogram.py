@@ -1,15 +1,15 @@
 """GPU parity of the histogram reduction (reduction(+: hist[0:bins]) with
 hist[key[i]] += 1) against the oracle, exact: bin counts from 1 to 9 000 000
 (team copies in LDS -- up to 40 704 bins with gfx950's 160 KiB a workgroup;
-two to four ranges of bins, each in LDS; from five ranges to 8 388 608 bins the
-keys partitioned by range of 32 768 bins, then each range counted in LDS;
-beyond, atomics on hist itself; on request ranges up to 32 of them, the
-partition for any bin count up to 8 388 608, team copies in the global pool,
-or atomics on hist for any bin count),
-uniform and
-single-key (fully contended) inputs, an incoming histogram taking part,
-keys out of range (skipped and flagged), several launch configurations and
-repeated launches."""
+two ranges of bins, each in LDS; then the keys partitioned by range of 32 768
+bins and each range counted in LDS -- up to 4 194 304 bins every tile of keys
+sorted by range into a slot of its own, up to 8 388 608 the ranges laid out
+across teams; beyond, atomics on hist itself; on request ranges up to 32 of
+them, either partition for any bin count it takes, team copies in the global
+pool, or atomics on hist for any bin count), uniform, skewed and single-key
+(fully contended) inputs, an incoming histogram taking part, keys out of
+range (skipped and flagged), several launch configurations and team counts,
+and repeated launches."""
 import numpy as np
 import pytest
 import torch
