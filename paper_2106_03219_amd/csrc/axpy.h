@@ -351,6 +351,172 @@ __device__ __forceinline__ void axpy_run_lines(float a, const float* __restrict_
     if (r < hi) axpy_range(a, x, y, r, hi, acc);
 }
 
+// Runs of the 64 lanes of a wave that lie side by side in lane order (lane
+// l's run ends where lane l + 1's starts), moved as one union [ulo, uhi):
+// pass q holds 64 consecutive 128-byte lines of the union (instruction k,
+// lane i moves block (i & 7) ^ line_swz(p) of line p = 8k + i/8, the LDS
+// layout of AxpyLines), and every lane executes the elements of its own run
+// that the pass holds, from LDS, in increasing order.  Blocks wholly inside
+// the union move as 16-byte vectors, the union's first and last blocks
+// element by element; nothing outside it is read or written.  For short
+// runs (a pass holds 2048 elements: with runs of r elements about 2048 / r
+// lanes compute in it), whatever their alignment: no lane has edges of its
+// own.  Loads run two passes ahead (line_passes).
+struct AxpyUnion {
+    static constexpr int64_t kLine = kLineBytes / 4;
+    static constexpr int64_t kPass = kLine * kWave;   // elements a pass holds
+    float a;
+    const float* __restrict__ x;
+    float* __restrict__ y;
+    f32x4* __restrict__ xs;
+    f32x4* __restrict__ ys;
+    ff_t* acc;
+    // offsets in elements from x + u0 / y + u0, the first element of the
+    // union's first line (the union of short runs spans under 2^31)
+    int32_t ulo, uhi;   // the union
+    int32_t lo, hi;     // this lane's run
+    int32_t src[8];     // the block this lane moves in pass 0, instruction k
+    f32x4 vx[2][8], vy[2][8];
+
+    template <int SET>
+    __device__ __forceinline__ void load(int64_t q) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int32_t e = (int32_t)q * (int32_t)kPass + src[k];
+            if (e >= ulo && e + 4 <= uhi) {
+                vx[SET][k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(x + e));
+                vy[SET][k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(y + e));
+            } else if (e + 4 > ulo && e < uhi) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (e + u >= ulo && e + u < uhi) {
+                        vx[SET][k][u] = x[e + u];
+                        vy[SET][k][u] = y[e + u];
+                    }
+            }
+        }
+    }
+    template <int SET>
+    __device__ __forceinline__ void pass(int64_t q, int64_t np) {
+        const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            xs[kWave * k + lane] = vx[SET][k];
+            ys[kWave * k + lane] = vy[SET][k];
+        }
+        if (q + 2 < np) load<SET>(q + 2);
+        wave_lds_order();
+        const int32_t w0 = (int32_t)q * (int32_t)kPass;
+        const int r0 = (lo > w0 ? lo : w0) - w0;
+        const int r1 = (hi < w0 + (int32_t)kPass ? hi : w0 + (int32_t)kPass) - w0;
+        auto slot_of = [](int r) {
+            const int pl = r >> 5;
+            return kLineSlots * pl + (((r >> 2) & 7) ^ line_swz(pl));
+        };
+        auto one = [&](int r) {
+            float* xf = reinterpret_cast<float*>(xs + slot_of(r));
+            float* yf = reinterpret_cast<float*>(ys + slot_of(r));
+            const float v = __builtin_fmaf(a, xf[r & 3], yf[r & 3]);
+            yf[r & 3] = v;
+            comp_add(*acc, v);
+        };
+        // the lane's elements of the pass: up to a 16-byte block boundary one
+        // by one, then whole blocks (two loaded ahead of their use), then the rest
+        int r = r0;
+        for (; r < r1 && (r & 3); ++r) one(r);
+        for (; r + 8 <= r1; r += 8) {
+            const int sa = slot_of(r), sb = slot_of(r + 4);
+            const f32x4 xa = xs[sa], xb = xs[sb];
+            f32x4 ya = ys[sa], yb = ys[sb];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ya[u] = __builtin_fmaf(a, xa[u], ya[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) yb[u] = __builtin_fmaf(a, xb[u], yb[u]);
+            ys[sa] = ya;
+            ys[sb] = yb;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) comp_add(*acc, ya[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) comp_add(*acc, yb[u]);
+        }
+        for (; r + 4 <= r1; r += 4) {
+            const int sa = slot_of(r);
+            const f32x4 xa = xs[sa];
+            f32x4 ya = ys[sa];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ya[u] = __builtin_fmaf(a, xa[u], ya[u]);
+            ys[sa] = ya;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) comp_add(*acc, ya[u]);
+        }
+        for (; r < r1; ++r) one(r);
+        wave_lds_order();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int32_t e = w0 + src[k];
+            const f32x4 v = ys[kWave * k + lane];
+            if (e >= ulo && e + 4 <= uhi) {
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(y + e));
+            } else if (e + 4 > ulo && e < uhi) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (e + u >= ulo && e + u < uhi) y[e + u] = v[u];
+            }
+        }
+        wave_lds_order();
+    }
+};
+
+// One run [lo, hi) of the calling lane, wave-collective: through AxpyUnion
+// when the wave's runs lie side by side (as the static schedules' rounds
+// do), else the lane alone.
+constexpr int64_t kUnionRun = 128;   // the longest runs the union path is for
+__device__ __forceinline__ void axpy_union_lines(float a, const float* __restrict__ x,
+                                                 float* __restrict__ y, int64_t lo, int64_t hi,
+                                                 f32x4* __restrict__ xs, f32x4* __restrict__ ys,
+                                                 ff_t* acc);
+__device__ __forceinline__ void axpy_run_union(float a, const float* __restrict__ x,
+                                               float* __restrict__ y, int64_t lo, int64_t hi,
+                                               f32x4* __restrict__ xs, f32x4* __restrict__ ys,
+                                               ff_t& acc) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t next_lo = __shfl_down(lo, 1, kWave);
+    const bool joined = lane == kWave - 1 || hi == next_lo;
+    if (__ballot(joined) != ~0ull) {
+        axpy_range(a, x, y, lo, hi, acc);
+        return;
+    }
+    axpy_union_lines(a, x, y, lo, hi, xs, ys, &acc);
+}
+
+// The union of the wave's runs through AxpyUnion (the runs lie side by side).
+__device__ __forceinline__ void axpy_union_lines(float a, const float* __restrict__ x,
+                                                 float* __restrict__ y, int64_t lo, int64_t hi,
+                                                 f32x4* __restrict__ xs, f32x4* __restrict__ ys,
+                                                 ff_t* acc) {
+    const int lane = threadIdx.x & (kWave - 1);
+    AxpyUnion f;
+    f.a = a;
+    f.xs = xs;
+    f.ys = ys;
+    f.acc = acc;
+    const int64_t ulo = __shfl(lo, 0, kWave), uhi = __shfl(hi, kWave - 1, kWave);
+    const int64_t u0 = ulo - (int64_t)((reinterpret_cast<uintptr_t>(y + ulo) & (kLineBytes - 1)) / 4);
+    f.x = x + u0;
+    f.y = y + u0;
+    f.lo = (int32_t)(lo - u0);
+    f.hi = (int32_t)(hi - u0);
+    f.ulo = (int32_t)(ulo - u0);
+    f.uhi = (int32_t)(uhi - u0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int pl = 8 * k + (lane >> 3);
+        f.src[k] = (int32_t)(AxpyUnion::kLine * pl + 4 * ((lane & 7) ^ line_swz(pl)));
+    }
+    const int64_t nlines = (uhi - u0 + AxpyUnion::kLine - 1) / AxpyUnion::kLine;
+    line_passes(f, (nlines + kWave - 1) / kWave);
+}
+
 // End of the region: the team tree, the cross-team publish and last-team
 // election, and sum[0] <- sum[0] + the launch's total (compensated).
 // epoch was read at the start of the kernel (when gridDim.x > 1).

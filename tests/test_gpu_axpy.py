@@ -44,7 +44,12 @@ SMALL = [(1, 1, 1, 0, 0), (100, 2, 64, 0, 0), (1000, 3, 9, 0, 1), (1000, 3, 9, 1
          # one team of 512 per compute unit; 1024 and more: 512 threads, ~128
          # chunks a team), ragged sizes
          (100003, 0, 0, 0, 1), (300001, 0, 0, 0, 1024), (1000003, 0, 0, 0, 4096),
-         (70000, 0, 0, 0, 4096)]
+         (70000, 0, 0, 0, 4096),
+         # short runs off the line grid through the union of a wave's runs:
+         # chunks 16 to 128, chunk 0 shares of up to 128, a final partial round
+         (200003, 8, 256, 0, 16), (200003, 8, 256, 0, 32), ((1 << 20) + 5, 32, 256, 0, 120),
+         (1000003, 64, 256, 0, 0), (1000003, 512, 64, 0, 0), (333333, 3, 128, 0, 48),
+         ((1 << 20), 4, 256, 0, 16), ((1 << 20) + 64, 4, 256, 0, 32)]
 
 
 @pytest.mark.parametrize("n,T,P,dc,c", SMALL)
