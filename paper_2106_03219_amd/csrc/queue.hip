@@ -130,11 +130,13 @@ __global__ __launch_bounds__(1024) void queue_map_kernel(QueueCfg qc, int64_t n,
 
 // ONE: dynamic chunks of one iteration (a separate instantiation, so that
 // the register-hungry run code of the other schedules does not cut its
-// occupancy: this path is bound by memory latency).  LINES: when a whole
+// occupancy: this path is bound by memory latency).  MODE: when a whole
 // wave takes tickets and every lane's chunk of a round exists, the wave's
 // chunks (neighbouring chunk numbers, so side by side in memory) run
-// through a per-wave LDS buffer of 16 KiB (lines.h) instead of lane by lane.
-template <bool ONE, bool LINES>
+// through a per-wave LDS buffer of 16 KiB (lines.h) instead of lane by lane:
+// each lane's run a line per pass (MODE 1), or the union of the wave's runs
+// (MODE 2, for dynamic chunks of 16 to kUnionRun iterations).
+template <bool ONE, int MODE>
 __global__ __launch_bounds__(512) void queue_axpy_kernel(QueueCfg qc, float a,
                                                           const float* __restrict__ x,
                                                           float* __restrict__ y,
@@ -186,13 +188,16 @@ __global__ __launch_bounds__(512) void queue_axpy_kernel(QueueCfg qc, float a,
                 } else {
                     for (int j = 0; j < qc.tickets; ++j) {
                         const int64_t tk = g.first + (int64_t)j * g.stride;
-                        if (LINES && g.stride == kWave &&
+                        if (MODE && g.stride == kWave &&
                             read_lane64((uint64_t)tk, kWave - 1) < (uint64_t)bq.nchunks) {
                             // the whole wave holds chunks this round (chunk
                             // numbers grow with the lane)
                             f32x4* xs = stage + (size_t)(t / kWave) * (2 * kStageSlots);
                             const Range ch = bq.chunk(tk);
-                            axpy_run_lines(a, xb, yb, ch.lo, ch.hi, xs, xs + kStageSlots, acc);
+                            if (MODE == 2)
+                                axpy_run_union(a, xb, yb, ch.lo, ch.hi, xs, xs + kStageSlots, acc);
+                            else
+                                axpy_run_lines(a, xb, yb, ch.lo, ch.hi, xs, xs + kStageSlots, acc);
                             continue;
                         }
                         if (tk >= bq.nchunks) break;
@@ -408,24 +413,44 @@ extern "C" omprt_status omprt_axpy_sum_queue(float a, const float* d_x, float* d
     const int block = (threads + kWave - 1) / kWave * kWave;
     // lines for chunks of at least 64 iterations (dynamic) and for guided
     // chunks (they start at m / P iterations), teams of whole waves, x and y
-    // co-aligned to 16 bytes
-    const bool lines = threads % kWave == 0 && (kind == KIND_GUIDED || qc.cmin >= 64) &&
-                       ((reinterpret_cast<uintptr_t>(d_x) ^ reinterpret_cast<uintptr_t>(d_y)) & 15) == 0;
+    // co-aligned to 16 bytes; dynamic chunks of 32 to 64 iterations (16 to
+    // 31 when the team blocks are off the 32-element grid of y) as the union
+    // of the wave's runs, except whole-line chunks of 64.  2^26 fp32, one
+    // team of 256 a CU: chunk 32 4.03 -> 5.06 TB/s; blocks off the grid:
+    // chunk 16 2.03 -> 3.03, 32 2.66 -> 3.32, 64 3.04 -> 3.87; longer chunks
+    // (100, 128) and chunk 16 on the grid ran slower through the union
+    // (four waves a CU hide less of its per-lane LDS work than the static
+    // schedules' eight).
+    const bool co = ((reinterpret_cast<uintptr_t>(d_x) ^ reinterpret_cast<uintptr_t>(d_y)) & 15) == 0;
+    const bool waves = threads % kWave == 0;
+    const bool on_grid = (reinterpret_cast<uintptr_t>(d_y) & (kLineBytes - 1)) == 0 &&
+                         (s->dist_chunk ? s->dist_chunk % 32 == 0
+                                        : s->n % teams == 0 && (s->n / teams) % 32 == 0);
+    const int64_t c = qc.cmin;
+    const bool union_runs = kind == KIND_DYNAMIC &&
+                            ((c >= 32 && c <= 64 && !(on_grid && c == 64)) ||
+                             (c >= 16 && c < 32 && !on_grid));
+    const bool lines = waves && co && (kind == KIND_GUIDED || qc.cmin >= 64);
     hipError_t e = hipSuccess;
-    if (kind == KIND_DYNAMIC && qc.cmin == 1) {
-        hipLaunchKernelGGL((queue_axpy_kernel<true, false>), dim3(teams), dim3(block), 0, stream,
-                           qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
-    } else if (!lines) {
-        hipLaunchKernelGGL((queue_axpy_kernel<false, false>), dim3(teams), dim3(block), 0, stream,
-                           qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
-    } else {
+    auto launch_staged = [&](auto kernel) {
         const size_t lds = (size_t)(threads / kWave) * 2 * kStageSlots * 16;
         if (lds > 64 * 1024)   // past the default dynamic LDS limit: ask for it
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(queue_axpy_kernel<false, true>),
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e == hipSuccess)
-            hipLaunchKernelGGL((queue_axpy_kernel<false, true>), dim3(teams), dim3(block), lds,
-                               stream, qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
+            hipLaunchKernelGGL(kernel, dim3(teams), dim3(block), lds, stream, qc, a, d_x, d_y,
+                               d_sum, s->n, s->dist_chunk, ct);
+    };
+    if (kind == KIND_DYNAMIC && qc.cmin == 1) {
+        hipLaunchKernelGGL((queue_axpy_kernel<true, 0>), dim3(teams), dim3(block), 0, stream,
+                           qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
+    } else if (waves && co && union_runs) {
+        launch_staged(queue_axpy_kernel<false, 2>);
+    } else if (lines) {
+        launch_staged(queue_axpy_kernel<false, 1>);
+    } else {
+        hipLaunchKernelGGL((queue_axpy_kernel<false, 0>), dim3(teams), dim3(block), 0, stream,
+                           qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
     }
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return fail(OMPRT_ERR_DEVICE, "queue axpy launch: %s", hipGetErrorString(e));
