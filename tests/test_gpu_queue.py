@@ -60,7 +60,11 @@ AXPY = [(1000, 3, 96, 0, 0), (100003, 13, 96, 0, 1), (100003, 13, 96, 1000, 3), 
         (1 << 20, 0, 0, 0, 1), (1 << 20, 0, 0, 0, 0), (5000, 2, 130, 0, 2),
         # whole-wave teams with long chunks (through LDS lines): ragged chunk
         # sizes and block starts, distribute blocks, a final partial round
-        ((1 << 20) + 37, 5, 192, 0, 100), (300000, 7, 512, 30011, 64), ((1 << 20) + 3, 3, 128, 0, 2048)]
+        ((1 << 20) + 37, 5, 192, 0, 100), (300000, 7, 512, 30011, 64), ((1 << 20) + 3, 3, 128, 0, 2048),
+        # short dynamic chunks as the union of a wave's runs: on and off the
+        # line grid, a final partial round, the runtime's own team size
+        ((1 << 20) + 37, 5, 192, 0, 16), ((1 << 20), 4, 256, 0, 32), (300001, 7, 256, 0, 48),
+        ((1 << 20) + 11, 0, 0, 0, 64), (200003, 3, 64, 0, 24), ((1 << 20), 8, 512, 0, 64)]
 
 
 @pytest.mark.parametrize("kind", ["dynamic", "guided"])
