@@ -361,8 +361,10 @@ __device__ __forceinline__ void axpy_run_lines(float a, const float* __restrict_
 // element by element; nothing outside it is read or written.  For short
 // runs (a pass holds 2048 elements: with runs of r elements about 2048 / r
 // lanes compute in it), whatever their alignment: no lane has edges of its
-// own.  Loads run two passes ahead (line_passes).
-struct AxpyUnion {
+// own.  Loads run two passes ahead (line_passes).  AXPY false: the fold of
+// the sum alone (y read, the owner adding its elements; nothing stored).
+template <bool AXPY>
+struct AxpyUnionT {
     static constexpr int64_t kLine = kLineBytes / 4;
     static constexpr int64_t kPass = kLine * kWave;   // elements a pass holds
     float a;
@@ -384,13 +386,14 @@ struct AxpyUnion {
         for (int k = 0; k < 8; ++k) {
             const int32_t e = (int32_t)q * (int32_t)kPass + src[k];
             if (e >= ulo && e + 4 <= uhi) {
-                vx[SET][k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(x + e));
+                if (AXPY)
+                    vx[SET][k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(x + e));
                 vy[SET][k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(y + e));
             } else if (e + 4 > ulo && e < uhi) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     if (e + u >= ulo && e + u < uhi) {
-                        vx[SET][k][u] = x[e + u];
+                        if (AXPY) vx[SET][k][u] = x[e + u];
                         vy[SET][k][u] = y[e + u];
                     }
             }
@@ -401,7 +404,7 @@ struct AxpyUnion {
         const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            xs[kWave * k + lane] = vx[SET][k];
+            if (AXPY) xs[kWave * k + lane] = vx[SET][k];
             ys[kWave * k + lane] = vy[SET][k];
         }
         if (q + 2 < np) load<SET>(q + 2);
@@ -414,11 +417,21 @@ struct AxpyUnion {
             return kLineSlots * pl + (((r >> 2) & 7) ^ line_swz(pl));
         };
         auto one = [&](int r) {
-            float* xf = reinterpret_cast<float*>(xs + slot_of(r));
             float* yf = reinterpret_cast<float*>(ys + slot_of(r));
-            const float v = __builtin_fmaf(a, xf[r & 3], yf[r & 3]);
-            yf[r & 3] = v;
-            comp_add(*acc, v);
+            if (AXPY) {
+                const float* xf = reinterpret_cast<const float*>(xs + slot_of(r));
+                const float v = __builtin_fmaf(a, xf[r & 3], yf[r & 3]);
+                yf[r & 3] = v;
+                comp_add(*acc, v);
+            } else {
+                comp_add(*acc, yf[r & 3]);
+            }
+        };
+        auto block = [&](f32x4& yy, const f32x4& xx) {
+            if (AXPY) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) yy[u] = __builtin_fmaf(a, xx[u], yy[u]);
+            }
         };
         // the lane's elements of the pass: up to a 16-byte block boundary one
         // by one, then whole blocks (two loaded ahead of their use), then the rest
@@ -426,14 +439,18 @@ struct AxpyUnion {
         for (; r < r1 && (r & 3); ++r) one(r);
         for (; r + 8 <= r1; r += 8) {
             const int sa = slot_of(r), sb = slot_of(r + 4);
-            const f32x4 xa = xs[sa], xb = xs[sb];
+            f32x4 xa = {}, xb = {};
+            if (AXPY) {
+                xa = xs[sa];
+                xb = xs[sb];
+            }
             f32x4 ya = ys[sa], yb = ys[sb];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) ya[u] = __builtin_fmaf(a, xa[u], ya[u]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) yb[u] = __builtin_fmaf(a, xb[u], yb[u]);
-            ys[sa] = ya;
-            ys[sb] = yb;
+            block(ya, xa);
+            block(yb, xb);
+            if (AXPY) {
+                ys[sa] = ya;
+                ys[sb] = yb;
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) comp_add(*acc, ya[u]);
 #pragma unroll
@@ -441,36 +458,40 @@ struct AxpyUnion {
         }
         for (; r + 4 <= r1; r += 4) {
             const int sa = slot_of(r);
-            const f32x4 xa = xs[sa];
+            f32x4 xa = {};
+            if (AXPY) xa = xs[sa];
             f32x4 ya = ys[sa];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) ya[u] = __builtin_fmaf(a, xa[u], ya[u]);
-            ys[sa] = ya;
+            block(ya, xa);
+            if (AXPY) ys[sa] = ya;
 #pragma unroll
             for (int u = 0; u < 4; ++u) comp_add(*acc, ya[u]);
         }
         for (; r < r1; ++r) one(r);
         wave_lds_order();
+        if (AXPY) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int32_t e = w0 + src[k];
-            const f32x4 v = ys[kWave * k + lane];
-            if (e >= ulo && e + 4 <= uhi) {
-                __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(y + e));
-            } else if (e + 4 > ulo && e < uhi) {
+            for (int k = 0; k < 8; ++k) {
+                const int32_t e = w0 + src[k];
+                const f32x4 v = ys[kWave * k + lane];
+                if (e >= ulo && e + 4 <= uhi) {
+                    __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(y + e));
+                } else if (e + 4 > ulo && e < uhi) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (e + u >= ulo && e + u < uhi) y[e + u] = v[u];
+                    for (int u = 0; u < 4; ++u)
+                        if (e + u >= ulo && e + u < uhi) y[e + u] = v[u];
+                }
             }
+            wave_lds_order();
         }
-        wave_lds_order();
     }
 };
+using AxpyUnion = AxpyUnionT<true>;
 
 // One run [lo, hi) of the calling lane, wave-collective: through AxpyUnion
 // when the wave's runs lie side by side (as the static schedules' rounds
 // do), else the lane alone.
 constexpr int64_t kUnionRun = 128;   // the longest runs the union path is for
+template <bool AXPY = true>
 __device__ __forceinline__ void axpy_union_lines(float a, const float* __restrict__ x,
                                                  float* __restrict__ y, int64_t lo, int64_t hi,
                                                  f32x4* __restrict__ xs, f32x4* __restrict__ ys,
@@ -489,20 +510,21 @@ __device__ __forceinline__ void axpy_run_union(float a, const float* __restrict_
     axpy_union_lines(a, x, y, lo, hi, xs, ys, &acc);
 }
 
-// The union of the wave's runs through AxpyUnion (the runs lie side by side).
+// The union of the wave's runs through AxpyUnionT (the runs lie side by side).
+template <bool AXPY>
 __device__ __forceinline__ void axpy_union_lines(float a, const float* __restrict__ x,
                                                  float* __restrict__ y, int64_t lo, int64_t hi,
                                                  f32x4* __restrict__ xs, f32x4* __restrict__ ys,
                                                  ff_t* acc) {
     const int lane = threadIdx.x & (kWave - 1);
-    AxpyUnion f;
+    AxpyUnionT<AXPY> f;
     f.a = a;
     f.xs = xs;
     f.ys = ys;
     f.acc = acc;
     const int64_t ulo = __shfl(lo, 0, kWave), uhi = __shfl(hi, kWave - 1, kWave);
     const int64_t u0 = ulo - (int64_t)((reinterpret_cast<uintptr_t>(y + ulo) & (kLineBytes - 1)) / 4);
-    f.x = x + u0;
+    f.x = AXPY ? x + u0 : x;
     f.y = y + u0;
     f.lo = (int32_t)(lo - u0);
     f.hi = (int32_t)(hi - u0);
@@ -511,9 +533,9 @@ __device__ __forceinline__ void axpy_union_lines(float a, const float* __restric
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int pl = 8 * k + (lane >> 3);
-        f.src[k] = (int32_t)(AxpyUnion::kLine * pl + 4 * ((lane & 7) ^ line_swz(pl)));
+        f.src[k] = (int32_t)(AxpyUnionT<AXPY>::kLine * pl + 4 * ((lane & 7) ^ line_swz(pl)));
     }
-    const int64_t nlines = (uhi - u0 + AxpyUnion::kLine - 1) / AxpyUnion::kLine;
+    const int64_t nlines = (uhi - u0 + AxpyUnionT<AXPY>::kLine - 1) / AxpyUnionT<AXPY>::kLine;
     line_passes(f, (nlines + kWave - 1) / kWave);
 }
 

@@ -54,6 +54,22 @@ __device__ __forceinline__ void sum_range(const float* __restrict__ y, int64_t l
     for (i += nv * 4; i < hi; ++i) comp_add(acc, y[i]);
 }
 
+// Loop 2's share of a union (axpy_run_union's geometry: under nowait the lane
+// that loads a block of y is the lane that stored it in loop 1), else the
+// lane alone.
+__device__ __forceinline__ void sum_run_union(const float* __restrict__ y, int64_t lo, int64_t hi,
+                                              f32x4* __restrict__ xs, f32x4* __restrict__ ys,
+                                              ff_t& acc) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t next_lo = __shfl_down(lo, 1, kWave);
+    const bool joined = lane == kWave - 1 || hi == next_lo;
+    if (__ballot(joined) != ~0ull) {
+        sum_range(y, lo, hi, acc);
+        return;
+    }
+    axpy_union_lines<false>(0.0f, nullptr, const_cast<float*>(y), lo, hi, xs, ys, &acc);
+}
+
 // Chunk size 1: thread t reads lo + t, lo + t + P, ... (coalesced across
 // the wave), eight rows in flight.
 __device__ __forceinline__ void sum_stride(const float* __restrict__ y, int64_t lo, int64_t hi,
@@ -70,14 +86,15 @@ __device__ __forceinline__ void sum_stride(const float* __restrict__ y, int64_t 
     for (; i < hi; i += P) comp_add(acc, y[i]);
 }
 
-// LINES: the lane runs of the first lw1 (loop 1) / lw2 (loop 2) waves of a
+// MODE 1: the lane runs of the first lw1 (loop 1) / lw2 (loop 2) waves of a
 // team go through a per-wave LDS buffer (lines.h; 16 KiB a wave of dynamic
-// shared memory).  With nowait both loops have the same schedule, so lw1 ==
-// lw2 and a wave splits every run the same way in both: the lane that loads
-// a 16-byte block of y in loop 2 is the lane that stored it in loop 1, and
-// the heads and tails of the runs stay with their owners.
-template <bool NOWAIT, bool LINES>
-__global__ __launch_bounds__(LINES ? 512 : 1024) void region_axpy_then_sum_kernel(
+// shared memory); MODE 2: short runs as the union of the wave's runs in both
+// loops.  With nowait both loops have the same schedule, so lw1 == lw2 and a
+// wave splits every run the same way in both: the lane that loads a 16-byte
+// block of y in loop 2 is the lane that stored it in loop 1, and the heads
+// and tails of the runs stay with their owners.
+template <bool NOWAIT, int MODE>
+__global__ __launch_bounds__(MODE ? 512 : 1024) void region_axpy_then_sum_kernel(
     float a, const float* __restrict__ x, float* __restrict__ y, float* __restrict__ sum,
     int64_t n, int P, int64_t dc, int64_t c1, int64_t c2, int lw1, int lw2, CrossTeam ct) {
     using R = Red<DT_F32, OP_SUM>;
@@ -104,11 +121,14 @@ __global__ __launch_bounds__(LINES ? 512 : 1024) void region_axpy_then_sum_kerne
             }
             const int64_t nc = thread_nchunks(m, P, c1, t);
             int64_t j = 0;
-            if (LINES && wave < lw1) {
+            if (MODE && wave < lw1) {
                 const int64_t full = c1 == 0 ? 1 : thread_nchunks(m, P, c1, t | (kWave - 1));
                 for (; j < full; ++j) {
                     const Range ch = thread_chunk(blk.lo, m, P, c1, t, j);
-                    axpy_run_lines(a, x, y, ch.lo, ch.hi, xs, ys, unused);
+                    if (MODE == 2)
+                        axpy_run_union(a, x, y, ch.lo, ch.hi, xs, ys, unused);
+                    else
+                        axpy_run_lines(a, x, y, ch.lo, ch.hi, xs, ys, unused);
                 }
             }
             for (; j < nc; ++j) {
@@ -131,7 +151,13 @@ __global__ __launch_bounds__(LINES ? 512 : 1024) void region_axpy_then_sum_kerne
             }
             const int64_t nc = thread_nchunks(m, P, c2, t);
             int64_t j = 0;
-            if (LINES && wave < lw2) {
+            if (MODE == 2 && wave < lw2) {
+                const int64_t full = c2 == 0 ? 1 : thread_nchunks(m, P, c2, t | (kWave - 1));
+                for (; j < full; ++j) {
+                    const Range ch = thread_chunk(blk.lo, m, P, c2, t, j);
+                    sum_run_union(y, ch.lo, ch.hi, xs, ys, acc);
+                }
+            } else if (MODE == 1 && wave < lw2) {
                 const int64_t full = c2 == 0 ? 1 : thread_nchunks(m, P, c2, t | (kWave - 1));
                 for (; j < full; ++j) {
                     const Range ch = thread_chunk(blk.lo, m, P, c2, t, j);
@@ -157,27 +183,65 @@ static hipError_t launch_region(float a, const float* x, float* y, float* sum, i
                                 int teams, int threads, int64_t dc, int64_t c1, int64_t c2,
                                 const CrossTeam& ct, hipStream_t stream) {
     constexpr int64_t kMinChunk = 64;
+    constexpr int64_t kUnionMinChunk = 16;
     const int block = (threads + kWave - 1) / kWave * kWave;
     const bool co_aligned =
         ((reinterpret_cast<uintptr_t>(x) ^ reinterpret_cast<uintptr_t>(y)) & 15) == 0;
+    // Short runs off the line grid (both loops) as the union of the wave's
+    // runs, whole-line runs through the lane-run lines, as for the AXPY body
+    // alone.
+    const int64_t m_hi = dc ? std::min<int64_t>(dc, n) : (n + teams - 1) / teams;
+    const bool blocks_on_grid = (reinterpret_cast<uintptr_t>(y) & (kLineBytes - 1)) == 0 &&
+                                (dc ? dc % 32 == 0 : n % teams == 0 && (n / teams) % 32 == 0);
+    auto whole = [&](int64_t c) {
+        return blocks_on_grid && (c > 0 ? c % 32 == 0
+                                        : (n / teams) % threads == 0 &&
+                                              (n / teams / threads) % 32 == 0);
+    };
+    // (runs of up to 64: longer ones, e.g. chunk 100, ran slower through the
+    // union in the two-loop region, 4.47 -> 3.83 TB/s)
+    constexpr int64_t kRegionUnionRun = 64;
+    auto short_runs = [&](int64_t c) {
+        return c > 0 ? c >= kUnionMinChunk && c <= kRegionUnionRun
+                     : (m_hi + threads - 1) / threads <= kRegionUnionRun;
+    };
     int lw1 = co_aligned ? lines_waves(n, teams, threads, dc, c1, 4, kMinChunk, 512) : 0;
     int lw2 = lines_waves(n, teams, threads, dc, c2, 4, kMinChunk, 512);
     if (NOWAIT) lw1 = lw2 = std::min(lw1, lw2);   // the same split of every run in both loops
-    const int lw = std::max(lw1, lw2);
-    if (lw == 0) {
-        hipLaunchKernelGGL((region_axpy_then_sum_kernel<NOWAIT, false>), dim3(teams), dim3(block),
-                           0, stream, a, x, y, sum, n, threads, dc, c1, c2, 0, 0, ct);
+    int mode = std::max(lw1, lw2) ? 1 : 0;
+    const bool lines_whole = lw1 && lw2 && whole(c1) && whole(c2);
+    if (!lines_whole && co_aligned && threads % kWave == 0 && threads <= 512 && n > 0 &&
+        short_runs(c1) && short_runs(c2) && c1 != 1 && c2 != 1) {
+        mode = 2;
+        auto uw = [&](int64_t c) {
+            return c > 0 ? lines_waves(n, teams, threads, dc, c, 4, kUnionMinChunk, 512)
+                         : threads / kWave;
+        };
+        lw1 = uw(c1);
+        lw2 = uw(c2);
+        if (NOWAIT) lw1 = lw2 = std::min(lw1, lw2);
+        if (std::max(lw1, lw2) == 0) mode = 0;
+    }
+    if (mode == 0) {
+        hipLaunchKernelGGL((region_axpy_then_sum_kernel<NOWAIT, 0>), dim3(teams), dim3(block), 0,
+                           stream, a, x, y, sum, n, threads, dc, c1, c2, 0, 0, ct);
         return hipGetLastError();
     }
-    const size_t lds = (size_t)lw * 2 * kStageSlots * 16;
+    const size_t lds = (size_t)std::max(lw1, lw2) * 2 * kStageSlots * 16;
+    const void* fn = mode == 2
+                         ? reinterpret_cast<const void*>(region_axpy_then_sum_kernel<NOWAIT, 2>)
+                         : reinterpret_cast<const void*>(region_axpy_then_sum_kernel<NOWAIT, 1>);
     if (lds > 64 * 1024) {   // past the default dynamic LDS limit: ask for it
-        const hipError_t attr = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(region_axpy_then_sum_kernel<NOWAIT, true>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const hipError_t attr =
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (attr != hipSuccess) return attr;
     }
-    hipLaunchKernelGGL((region_axpy_then_sum_kernel<NOWAIT, true>), dim3(teams), dim3(block), lds,
-                       stream, a, x, y, sum, n, threads, dc, c1, c2, lw1, lw2, ct);
+    if (mode == 2)
+        hipLaunchKernelGGL((region_axpy_then_sum_kernel<NOWAIT, 2>), dim3(teams), dim3(block),
+                           lds, stream, a, x, y, sum, n, threads, dc, c1, c2, lw1, lw2, ct);
+    else
+        hipLaunchKernelGGL((region_axpy_then_sum_kernel<NOWAIT, 1>), dim3(teams), dim3(block),
+                           lds, stream, a, x, y, sum, n, threads, dc, c1, c2, lw1, lw2, ct);
     return hipGetLastError();
 }
 
