@@ -261,8 +261,10 @@ __device__ __forceinline__ void axpy_stride(float a, const float* __restrict__ x
 // every lane.  Each pass loads one line of x and of y per lane, eight lanes
 // a line, into LDS; the owner runs y[i] <- fmaf(a, x[i], y[i]) and its sum
 // over its line from LDS in increasing i, and the wave stores the updated
-// lines back eight lanes a line.  Loads run two passes ahead (line_passes),
-// so a wave keeps 32 KiB in flight through the LDS work of a pass.
+// lines back eight lanes a line.  The lines come in line_rot's order (ROT)
+// or in increasing order; loads run two passes ahead (line_passes), so a
+// wave keeps 32 KiB in flight through the LDS work of a pass.
+template <bool ROT>
 struct AxpyLines {
     static constexpr int64_t kLine = kLineBytes / 4;
     float a;
@@ -272,16 +274,18 @@ struct AxpyLines {
     f32x4* __restrict__ ys;
     ff_t* acc;
     int64_t src[8];
+    int64_t np, rot;
     f32x4 vx[2][8], vy[2][8];
 
     template <int SET>
     __device__ __forceinline__ void load(int64_t q) {
+        const int64_t l = rot_line<ROT>(q, rot, np) * kLine;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             vx[SET][k] = __builtin_nontemporal_load(
-                reinterpret_cast<const f32x4*>(x + src[k] + q * kLine));
+                reinterpret_cast<const f32x4*>(x + src[k] + l));
             vy[SET][k] = __builtin_nontemporal_load(
-                reinterpret_cast<const f32x4*>(y + src[k] + q * kLine));
+                reinterpret_cast<const f32x4*>(y + src[k] + l));
         }
     }
     template <int SET>
@@ -311,25 +315,29 @@ struct AxpyLines {
             comp_add(*acc, yy.w);
         }
         wave_lds_order();
+        const int64_t l = rot_line<ROT>(q, rot, np) * kLine;
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             __builtin_nontemporal_store(ys[kWave * k + lane],
-                                        reinterpret_cast<f32x4*>(y + src[k] + q * kLine));
+                                        reinterpret_cast<f32x4*>(y + src[k] + l));
         wave_lds_order();
     }
 };
 
+template <bool ROT>
 __device__ __forceinline__ void axpy_lines(float a, const float* __restrict__ x,
                                            float* __restrict__ y, int64_t mine, int64_t np,
                                            f32x4* __restrict__ xs, f32x4* __restrict__ ys,
                                            ff_t& acc) {
-    AxpyLines f;
+    AxpyLines<ROT> f;
     f.a = a;
     f.x = x;
     f.y = y;
     f.xs = xs;
     f.ys = ys;
     f.acc = &acc;
+    f.np = np;
+    f.rot = ROT ? line_rot(np) : 0;
     line_sources<4>(mine, f.src);
     line_passes(f, np);
 }
@@ -338,7 +346,9 @@ __device__ __forceinline__ void axpy_lines(float a, const float* __restrict__ x,
 // wave calls it, with its own run): the part before y's next line boundary
 // by the lane alone, then as many whole lines as every lane of the wave has
 // through axpy_lines, then the rest by the lane alone.  A lane's iterations
-// stay in increasing order.
+// stay in increasing order within each line; the lines come in line_rot's
+// order (ROT) or in increasing order.
+template <bool ROT = true>
 __device__ __forceinline__ void axpy_run_lines(float a, const float* __restrict__ x,
                                                float* __restrict__ y, int64_t lo, int64_t hi,
                                                f32x4* __restrict__ xs, f32x4* __restrict__ ys,
@@ -346,7 +356,7 @@ __device__ __forceinline__ void axpy_run_lines(float a, const float* __restrict_
     int64_t l0, np;
     run_lines<4>(y, lo, hi, l0, np);
     if (l0 > lo) axpy_range(a, x, y, lo, l0, acc);
-    axpy_lines(a, x, y, l0, np, xs, ys, acc);
+    axpy_lines<ROT>(a, x, y, l0, np, xs, ys, acc);
     const int64_t r = l0 + np * (kLineBytes / 4);
     if (r < hi) axpy_range(a, x, y, r, hi, acc);
 }

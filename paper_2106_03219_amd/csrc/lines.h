@@ -9,8 +9,9 @@
 // instruction k carries lines 8k .. 8k+7 (eight lanes a line, 16 bytes
 // each), so it touches eight whole lines, into a per-wave LDS buffer; then
 // every lane reads its own line back and executes its iterations on it, in
-// order.  The lane that owns an iteration still executes it; the other
-// lanes only copy bytes between memory and LDS.
+// order (the lines themselves in a wave-dependent rotation, line_rot).  The
+// lane that owns an iteration still executes it; the other lanes only copy
+// bytes between memory and LDS.
 //
 // LDS layout of one buffer (64 lines, 512 16-byte slots): block b of line p
 // sits in slot 8p + (b ^ line_swz(p)).  The loaders' writes are contiguous
@@ -62,6 +63,31 @@ __device__ __forceinline__ void line_sources(int64_t mine, int64_t (&src)[8]) {
     }
 }
 
+// Lines in a wave-dependent order.  Lane runs a multiple of 4 KiB apart
+// (power-of-two chunks and team blocks) have every wave of the grid move
+// lines at the same offsets at the same time, and such launches stream at
+// 3.4-4.2 TB/s on gfx950 where runs at scattered offsets reach 4.7-5.0.  So
+// wave g of the grid takes its lines from line (11 g) mod np on and wraps
+// round: each lane still moves, and each owner still executes, the same
+// lines, in rotated order.  Runs of fewer than kRotMinLines lines (strides
+// under 2 KiB of fp32, where rotating measured slower) and callers that
+// use the plain order keep it.
+constexpr int64_t kRotMinLines = 16;
+
+__device__ __forceinline__ int64_t line_rot(int64_t np) {
+    if (np < kRotMinLines) return 0;
+    const uint32_t g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    return np <= 0x7fffffff ? (int64_t)((g * 11u) % (uint32_t)np) : (int64_t)(g * 11u);
+}
+
+// Line that pass q moves (0 <= q, rot < np); q itself in the plain order.
+template <bool ROT>
+__device__ __forceinline__ int64_t rot_line(int64_t q, int64_t rot, int64_t np) {
+    if (!ROT) return q;
+    const int64_t l = q + rot;
+    return l >= np ? l - np : l;
+}
+
 // The passes q = 0 .. np-1 of a line loop whose loads run two passes ahead
 // in two register sets: F provides load<S>(q) (issue the loads of pass q
 // into set S) and pass<S>(q, np) (stage set S, issue pass q + 2 into it if
@@ -83,9 +109,10 @@ __device__ __forceinline__ void line_passes(F& f, int64_t np) {
 // `mine` on (in + mine on a 128-byte boundary; np the same on every lane)
 // into acc (R::kNA accumulators), through a per-wave buffer of kStageSlots
 // 16-byte slots: each pass loads one line of every lane's run, eight lanes
-// a line, and the owner folds its line from LDS in increasing order; loads
-// run two passes ahead (line_passes).
-template <class R, int DT>
+// a line, and the owner folds its line from LDS in increasing order; the
+// lines come in line_rot's order (ROT) or in increasing order; loads run
+// two passes ahead (line_passes).
+template <class R, int DT, bool ROT>
 struct LineFold {
     using L = VecLoad<DT, 16>;
     using Vec = typename L::T;
@@ -96,13 +123,15 @@ struct LineFold {
     u32x4* __restrict__ buf;
     typename R::Acc* acc;
     int64_t src[8];
+    int64_t np, rot;
     Vec v[2][8];
 
     template <int SET>
     __device__ __forceinline__ void load(int64_t q) {
+        const int64_t e = rot_line<ROT>(q, rot, np) * kLine;
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            v[SET][k] = L::load(reinterpret_cast<const Vec*>(in + src[k] + q * kLine));
+            v[SET][k] = L::load(reinterpret_cast<const Vec*>(in + src[k] + e));
     }
     template <int SET>
     __device__ __forceinline__ void pass(int64_t q, int64_t np) {
@@ -124,14 +153,16 @@ struct LineFold {
     }
 };
 
-template <class R, int DT>
+template <class R, int DT, bool ROT = true>
 __device__ __forceinline__ void line_fold(const typename DType<DT>::S* __restrict__ in,
                                           int64_t mine, int64_t np, u32x4* __restrict__ buf,
                                           typename R::Acc* acc) {
-    LineFold<R, DT> f;
+    LineFold<R, DT, ROT> f;
     f.in = in;
     f.buf = buf;
     f.acc = acc;
+    f.np = np;
+    f.rot = ROT ? line_rot(np) : 0;
     line_sources<(int)sizeof(typename DType<DT>::S)>(mine, f.src);
     line_passes(f, np);
 }

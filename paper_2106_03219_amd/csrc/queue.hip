@@ -134,7 +134,10 @@ __global__ __launch_bounds__(1024) void queue_map_kernel(QueueCfg qc, int64_t n,
 // wave takes tickets and every lane's chunk of a round exists, the wave's
 // chunks (neighbouring chunk numbers, so side by side in memory) run
 // through a per-wave LDS buffer of 16 KiB (lines.h) instead of lane by lane:
-// each lane's run a line per pass (MODE 1), or the union of the wave's runs
+// each lane's run a line per pass (MODE 1: the lines of a wave in rotated
+// order, line_rot, for dynamic chunks, whose runs sit a multiple of 4 KiB
+// apart for power-of-two chunks; MODE 3: in increasing order, for guided
+// chunks, which rotating measured slower), or the union of the wave's runs
 // (MODE 2, for dynamic chunks of 16 to kUnionRun iterations).
 template <bool ONE, int MODE>
 __global__ __launch_bounds__(512) void queue_axpy_kernel(QueueCfg qc, float a,
@@ -197,7 +200,8 @@ __global__ __launch_bounds__(512) void queue_axpy_kernel(QueueCfg qc, float a,
                             if (MODE == 2)
                                 axpy_run_union(a, xb, yb, ch.lo, ch.hi, xs, xs + kStageSlots, acc);
                             else
-                                axpy_run_lines(a, xb, yb, ch.lo, ch.hi, xs, xs + kStageSlots, acc);
+                                axpy_run_lines<MODE == 1>(a, xb, yb, ch.lo, ch.hi, xs,
+                                                          xs + kStageSlots, acc);
                             continue;
                         }
                         if (tk >= bq.nchunks) break;
@@ -446,8 +450,10 @@ extern "C" omprt_status omprt_axpy_sum_queue(float a, const float* d_x, float* d
                            qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);
     } else if (waves && co && union_runs) {
         launch_staged(queue_axpy_kernel<false, 2>);
-    } else if (lines) {
+    } else if (lines && kind == KIND_DYNAMIC) {
         launch_staged(queue_axpy_kernel<false, 1>);
+    } else if (lines) {
+        launch_staged(queue_axpy_kernel<false, 3>);
     } else {
         hipLaunchKernelGGL((queue_axpy_kernel<false, 0>), dim3(teams), dim3(block), 0, stream,
                            qc, a, d_x, d_y, d_sum, s->n, s->dist_chunk, ct);

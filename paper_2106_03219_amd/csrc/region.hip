@@ -91,8 +91,10 @@ __device__ __forceinline__ void sum_stride(const float* __restrict__ y, int64_t 
 // shared memory); MODE 2: short runs as the union of the wave's runs in both
 // loops.  With nowait both loops have the same schedule, so lw1 == lw2 and a
 // wave splits every run the same way in both: the lane that loads a 16-byte
-// block of y in loop 2 is the lane that stored it in loop 1, and the heads
-// and tails of the runs stay with their owners.
+// block of y in loop 2 is the lane that stored it in loop 1 (the two loops
+// also take the lines in the same order: line_rot depends only on the wave
+// and the run's line count), and the heads and tails of the runs stay with
+// their owners.
 template <bool NOWAIT, int MODE>
 __global__ __launch_bounds__(MODE ? 512 : 1024) void region_axpy_then_sum_kernel(
     float a, const float* __restrict__ x, float* __restrict__ y, float* __restrict__ sum,
