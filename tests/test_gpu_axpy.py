@@ -59,6 +59,26 @@ def test_axpy_small_schedules(gpu_lib, n, T, P, dc, c):
     _run(gpu_lib, x, y, T, P, dc, c, s0=1.25)
 
 
+# Lane runs of 15 to 128 lines; from 16 lines on a wave takes its lines in a
+# rotated order that depends on the wave (so many teams give many starting
+# lines): chunks around that threshold, chunk-0 shares of 16, 17 and 100
+# lines a lane, ragged ends; each run again with x and y one element off the
+# line grid (a head before the first line, one line fewer).
+ROTATED = [(64 * 64 * 480 + 5, 64, 64, 0, 480), (37 * 64 * 512, 37, 64, 0, 512),
+           (37 * 64 * 544 + 3, 37, 64, 0, 544), (23 * 128 * 1056, 23, 128, 0, 1056),
+           (9 * 64 * 4096 + 77, 9, 64, 0, 4096), (41 * 256 * 512, 41, 256, 0, 0),
+           (41 * 256 * 544 + 100, 41, 256, 0, 0), (13 * 192 * 3200, 13, 192, 0, 0)]
+
+
+@pytest.mark.parametrize("n,T,P,dc,c", ROTATED)
+def test_axpy_rotated_lines(gpu_lib, n, T, P, dc, c):
+    x = synth.f32_normal(n, 70 + n % 1000)
+    y = synth.f32_normal(n, 71 + n % 1000)
+    ref = oracle.axpy_sum(A, x, y, 0.5)
+    _run(gpu_lib, x, y, T, P, dc, c, s0=0.5, ref=ref)
+    _run(gpu_lib, x, y, T, P, dc, c, s0=0.5, xoff=1, yoff=1, ref=ref)
+
+
 def test_axpy_misaligned(gpu_lib):
     x = synth.f32_normal(50001, 3)
     y = synth.f32_normal(50001, 4)

@@ -64,7 +64,9 @@ AXPY = [(1000, 3, 96, 0, 0), (100003, 13, 96, 0, 1), (100003, 13, 96, 1000, 3), 
         # short dynamic chunks as the union of a wave's runs: on and off the
         # line grid, a final partial round, the runtime's own team size
         ((1 << 20) + 37, 5, 192, 0, 16), ((1 << 20), 4, 256, 0, 32), (300001, 7, 256, 0, 48),
-        ((1 << 20) + 11, 0, 0, 0, 64), (200003, 3, 64, 0, 24), ((1 << 20), 8, 512, 0, 64)]
+        ((1 << 20) + 11, 0, 0, 0, 64), (200003, 3, 64, 0, 24), ((1 << 20), 8, 512, 0, 64),
+        # dynamic chunks of 16 and 17 lines (a wave's lines in a rotated order)
+        ((1 << 21) + 37, 5, 192, 0, 544), (37 * 64 * 1024, 37, 64, 0, 512)]
 
 
 @pytest.mark.parametrize("kind", ["dynamic", "guided"])

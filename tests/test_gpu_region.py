@@ -44,7 +44,7 @@ SCHEDS = [(1, 1, 1, 0), (100, 2, 64, 0), (1000, 3, 9, 0), (1000, 3, 9, 13), (409
 
 
 @pytest.mark.parametrize("n,T,P,dc", SCHEDS)
-@pytest.mark.parametrize("c", [0, 1, 7, 16, 32, 64, 1024])
+@pytest.mark.parametrize("c", [0, 1, 7, 16, 32, 64, 544, 1024])
 def test_nowait_and_barrier_same_schedule(gpu_lib, n, T, P, dc, c):
     x = synth.f32_normal(n, 50 + n)
     y = synth.f32_normal(n, 51 + n)
