@@ -344,10 +344,13 @@ __device__ __forceinline__ void axpy_lines(float a, const float* __restrict__ x,
 
 // One run [lo, hi) of the calling lane, wave-collective (every lane of the
 // wave calls it, with its own run): the part before y's next line boundary
-// by the lane alone, then as many whole lines as every lane of the wave has
-// through axpy_lines, then the rest by the lane alone.  A lane's iterations
-// stay in increasing order within each line; the lines come in line_rot's
-// order (ROT) or in increasing order.
+// and the part after as many whole lines as every lane of the wave has, by
+// the lane alone, then those whole lines through axpy_lines.  Both edges go
+// first: a run's last partial line is the next lane's first, and taken at
+// the same time the two halves share one fetch of the line (with the tail
+// after the lines, guided rounds ran 1-5 % slower).  A lane's iterations
+// stay in increasing order within each edge and line; the lines come in
+// line_rot's order (ROT) or in increasing order.
 template <bool ROT = true>
 __device__ __forceinline__ void axpy_run_lines(float a, const float* __restrict__ x,
                                                float* __restrict__ y, int64_t lo, int64_t hi,
@@ -355,10 +358,10 @@ __device__ __forceinline__ void axpy_run_lines(float a, const float* __restrict_
                                                ff_t& acc) {
     int64_t l0, np;
     run_lines<4>(y, lo, hi, l0, np);
-    if (l0 > lo) axpy_range(a, x, y, lo, l0, acc);
-    axpy_lines<ROT>(a, x, y, l0, np, xs, ys, acc);
     const int64_t r = l0 + np * (kLineBytes / 4);
+    if (l0 > lo) axpy_range(a, x, y, lo, l0, acc);
     if (r < hi) axpy_range(a, x, y, r, hi, acc);
+    axpy_lines<ROT>(a, x, y, l0, np, xs, ys, acc);
 }
 
 // Runs of the 64 lanes of a wave that lie side by side in lane order (lane
