@@ -158,21 +158,36 @@ int device_cus() {
 // up to 8 teams per CU, except for user chunks (2^26 fp32 on gfx950): the
 // AXPY's chunk 1 takes one team of 512 threads per CU (5.35 TB/s against
 // 4.95 with 8 teams of 256; the region's stays at 6.0 with the latter), and
-// chunks of 1024 iterations or more take 512 threads and about 128 chunks a
-// team (chunk 1024: 5.0 against 3.1 TB/s with 8 teams of 256 a CU, where
-// most lanes hold no chunk).
+// chunks of more than 512 iterations take 512 threads and about 128 chunks
+// a team (chunk 1024: 5.0 against 3.1 TB/s, chunk 768 5.3 against 3.5, with
+// 8 teams of 256 a CU, whose blocks of 32768 iterations hold less than a
+// wave's worth of such chunks; up to 512 the two launches run alike), the
+// team count rounded down to whole rounds of resident teams (one such team
+// a CU: 263 teams for chunk 2000 ran a second round for 7 teams, 3.1
+// against 4.8 TB/s with 256); with fewer than two waves' worth of chunks a
+// CU, the waves that hold chunks spread over all CUs (chunk 4096: 256 teams
+// of 64 threads, 4.3 against 3.8 TB/s with 128 teams of 512).
 static LaunchCfg heuristic(int64_t n, int dtype, int body, int64_t chunk) {
     LaunchCfg c = body ? LaunchCfg{0, 256, 16, 4} : LaunchCfg{0, 512, 16, 4};
     const int64_t bytes = n * (body ? 12 : dtype_bytes(dtype));
     const int64_t per = (int64_t)c.threads * c.vec * c.unroll;
     int64_t t = (bytes + per - 1) / per;
-    int64_t cap = body ? 8LL * device_cus() : (int64_t)device_cus();
+    const int64_t cus = device_cus();
+    int64_t cap = body ? 8 * cus : cus;
     if (body == 1 && chunk == 1) {
         c.threads = 512;
-        cap = device_cus();
-    } else if (body && chunk >= 1024) {
-        c.threads = 512;
-        t = (n + 128 * chunk - 1) / (128 * chunk);
+        cap = cus;
+    } else if (body && chunk > 512) {
+        constexpr int64_t kLanes = 64;                                          // a wave
+        const int64_t waves = ((n + chunk - 1) / chunk + kLanes - 1) / kLanes;  // waves of chunks
+        if (waves >= 2 * cus) {
+            c.threads = 512;
+            t = (n + 128 * chunk - 1) / (128 * chunk);
+            t = t / cus * cus;
+        } else {
+            t = std::min(waves, cus);
+            c.threads = (int)(kLanes * std::min<int64_t>((waves + t - 1) / t, 8));
+        }
     }
     t = std::min<int64_t>(std::max<int64_t>(t, 1), cap);
     c.teams = (int)t;

@@ -186,6 +186,29 @@ def test_resolve_config_precedence_and_heuristic():
         om.tune_set(om.I64, "max", 0, 20, {"teams": 33})   # must be complete
 
 
+def test_heuristic_large_user_chunks():
+    """The AXPY body's default launch for chunks of more than 512 iterations (256 compute units
+    without a GPU): 512 threads and about 128 chunks a team, rounded down to whole rounds of
+    one team per CU; with fewer than two waves' worth of chunks per CU, one team per wave of
+    chunks (at most one a CU) of 64 threads per wave.  Chunks up to 512 keep the body's
+    general launch (8 teams of 256 per CU at this size)."""
+    def pick(n, c):
+        cfg, src = om.resolve_config(n, om.F32, "sum", 1, c)
+        assert src == 3
+        return cfg["teams"], cfg["threads"]
+    n = 1 << 26
+    assert pick(n, 512) == (2048, 256)      # the general launch
+    assert pick(n, 768) == (512, 512)       # 683 rounded down to two rounds
+    assert pick(n, 1024) == (512, 512)
+    assert pick(n, 992) == (512, 512)       # 529 would leave a third round of 17 teams
+    assert pick(n, 2000) == (256, 512)      # 263 would leave a second round of 7
+    assert pick(n, 4096) == (256, 64)       # 256 waves of chunks, one a CU
+    assert pick(n, 8192) == (128, 64)
+    assert pick(300001, 1024) == (5, 64)    # 293 chunks: five waves
+    assert pick(n, n) == (1, 64)            # one chunk
+    assert pick(300 * 64 * 1024, 1024) == (256, 128)   # 300 waves: two a team on 44 CUs
+
+
 def test_model_features():
     f = om.model_features(1 << 20, om.F32, "sum", 0, -1)
     assert f[0] == 20.0 and f[3] == 1.0 and sum(f[1:6]) == 1.0
