@@ -56,13 +56,10 @@ struct LocRed {
     }
     static __device__ __forceinline__ Acc combine(Acc a, Acc b) { return before(b, a) ? b : a; }
     static __device__ __forceinline__ void elem(Acc& a, V v, int64_t i) {
-        // a lane meets its elements in increasing position: a tie keeps a
-        if constexpr (DT != DT_I32 && DT != DT_I64) {
-            if (v != v) return;
-            if (a.v != a.v || (OP == OP_MAX ? v > a.v : v < a.v)) a = make(v, i);
-        } else {
-            if (OP == OP_MAX ? v > a.v : v < a.v) a = make(v, i);
-        }
+        // a lane meets its elements in increasing position: a tie keeps a.  A
+        // NaN v fails the ordered compare, so it never wins, and a.v is never a
+        // NaN (it starts at the identity and only takes values that won).
+        if (OP == OP_MAX ? v > a.v : v < a.v) a = make(v, i);
     }
 };
 
