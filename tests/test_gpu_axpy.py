@@ -45,6 +45,10 @@ SMALL = [(1, 1, 1, 0, 0), (100, 2, 64, 0, 0), (1000, 3, 9, 0, 1), (1000, 3, 9, 1
          # chunks a team), ragged sizes
          (100003, 0, 0, 0, 1), (300001, 0, 0, 0, 1024), (1000003, 0, 0, 0, 4096),
          (70000, 0, 0, 0, 4096),
+         # chunks over 512 at the runtime's own launch: a team per wave of chunks (64
+         # threads; 128 with 300 waves of chunks), and 512 threads with the team count
+         # rounded down to whole rounds (33 001 chunks of 768: 258 -> 256 teams)
+         ((1 << 21) + 3, 0, 0, 0, 768), (11_520_007, 0, 0, 0, 600), (25_344_005, 0, 0, 0, 768),
          # short runs off the line grid through the union of a wave's runs:
          # chunks 16 to 128, chunk 0 shares of up to 128, a final partial round
          (200003, 8, 256, 0, 16), (200003, 8, 256, 0, 32), ((1 << 20) + 5, 32, 256, 0, 120),
