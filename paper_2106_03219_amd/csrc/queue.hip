@@ -419,14 +419,16 @@ extern "C" omprt_status omprt_axpy_sum_queue(float a, const float* d_x, float* d
     const int block = (threads + kWave - 1) / kWave * kWave;
     // lines for chunks of at least 64 iterations (dynamic) and for guided
     // chunks (they start at m / P iterations), teams of whole waves, x and y
-    // co-aligned to 16 bytes; dynamic chunks of 32 to 64 iterations (16 to
+    // co-aligned to 16 bytes; dynamic chunks of 32 to 64 iterations (8 to
     // 31 when the team blocks are off the 32-element grid of y) as the union
     // of the wave's runs, except whole-line chunks of 64.  2^26 fp32, one
     // team of 256 a CU: chunk 32 4.03 -> 5.06 TB/s; blocks off the grid:
     // chunk 16 2.03 -> 3.03, 32 2.66 -> 3.32, 64 3.04 -> 3.87; longer chunks
     // (100, 128) and chunk 16 on the grid ran slower through the union
     // (four waves a CU hide less of its per-lane LDS work than the static
-    // schedules' eight).
+    // schedules' eight).  Off the grid, chunks 8 and 12 (one team of 512 a
+    // CU): 1.84 -> 2.90 and 2.53 -> 3.87 TB/s through the union; chunks 2 and
+    // 4 ran slower through it (2.23 -> 0.97, 2.86 -> 1.92), 7 alike.
     const bool co = ((reinterpret_cast<uintptr_t>(d_x) ^ reinterpret_cast<uintptr_t>(d_y)) & 15) == 0;
     const bool waves = threads % kWave == 0;
     const bool on_grid = (reinterpret_cast<uintptr_t>(d_y) & (kLineBytes - 1)) == 0 &&
@@ -435,7 +437,7 @@ extern "C" omprt_status omprt_axpy_sum_queue(float a, const float* d_x, float* d
     const int64_t c = qc.cmin;
     const bool union_runs = kind == KIND_DYNAMIC &&
                             ((c >= 32 && c <= 64 && !(on_grid && c == 64)) ||
-                             (c >= 16 && c < 32 && !on_grid));
+                             (c >= 8 && c < 32 && !on_grid));
     const bool lines = waves && co && (kind == KIND_GUIDED || qc.cmin >= 64);
     hipError_t e = hipSuccess;
     auto launch_staged = [&](auto kernel) {

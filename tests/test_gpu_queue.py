@@ -65,6 +65,10 @@ AXPY = [(1000, 3, 96, 0, 0), (100003, 13, 96, 0, 1), (100003, 13, 96, 1000, 3), 
         # line grid, a final partial round, the runtime's own team size
         ((1 << 20) + 37, 5, 192, 0, 16), ((1 << 20), 4, 256, 0, 32), (300001, 7, 256, 0, 48),
         ((1 << 20) + 11, 0, 0, 0, 64), (200003, 3, 64, 0, 24), ((1 << 20), 8, 512, 0, 64),
+        # short dynamic chunks off the line grid (8 to 15: the union of a wave's runs;
+        # 7 and 4: lane by lane)
+        ((1 << 20) + 37, 5, 192, 0, 8), (300001, 7, 256, 0, 12), (200003, 3, 64, 0, 15),
+        (300001, 0, 0, 0, 8), ((1 << 20) + 37, 5, 192, 0, 7), (300001, 7, 256, 0, 4),
         # dynamic chunks of 16 and 17 lines (a wave's lines in a rotated order)
         ((1 << 21) + 37, 5, 192, 0, 544), (37 * 64 * 1024, 37, 64, 0, 512)]
 
