@@ -131,7 +131,11 @@ hipError_t launch_axpy_sum(float a, const float* x, float* y, float* sum, int64_
     const bool whole_runs =
         blocks_on_grid && (chunk > 0 ? chunk % 32 == 0
                                      : (n / teams) % threads == 0 && (n / teams / threads) % 32 == 0);
-    const bool short_runs = chunk > 0 ? chunk >= kUnionMinChunk && chunk <= kUnionRun
+    // off the grid from chunk 8 (2^26: chunk 8 1.90 -> 2.95 TB/s, 12 2.46 ->
+    // 3.96, 15 2.39 -> 4.32); on the grid chunks of 4 to 16 that are whole
+    // vectors take axpy_short_run instead
+    const int64_t union_min = blocks_on_grid ? kUnionMinChunk : 8;
+    const bool short_runs = chunk > 0 ? chunk >= union_min && chunk <= kUnionRun
                                       : (m_hi + threads - 1) / threads <= kUnionRun;
     int mode = 0, lw = 0;
     const int lw_lines =
@@ -141,7 +145,7 @@ hipError_t launch_axpy_sum(float a, const float* x, float* y, float* sum, int64_
         lw = lw_lines;
     } else if (co_aligned && waves && n > 0 && short_runs) {
         mode = 2;
-        lw = chunk > 0 ? lines_waves(n, teams, threads, dist_chunk, chunk, 4, kUnionMinChunk, 512)
+        lw = chunk > 0 ? lines_waves(n, teams, threads, dist_chunk, chunk, 4, union_min, 512)
                        : threads / kWave;
     } else if (lw_lines) {
         mode = 1;

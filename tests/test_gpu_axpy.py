@@ -53,7 +53,10 @@ SMALL = [(1, 1, 1, 0, 0), (100, 2, 64, 0, 0), (1000, 3, 9, 0, 1), (1000, 3, 9, 1
          # chunks 16 to 128, chunk 0 shares of up to 128, a final partial round
          (200003, 8, 256, 0, 16), (200003, 8, 256, 0, 32), ((1 << 20) + 5, 32, 256, 0, 120),
          (1000003, 64, 256, 0, 0), (1000003, 512, 64, 0, 0), (333333, 3, 128, 0, 48),
-         ((1 << 20), 4, 256, 0, 16), ((1 << 20) + 64, 4, 256, 0, 32)]
+         ((1 << 20), 4, 256, 0, 16), ((1 << 20) + 64, 4, 256, 0, 32),
+         # chunks of 8 to 15 with team blocks off the line grid (the union), and 7 (lane by lane)
+         ((1 << 20) + 5, 8, 256, 0, 8), (300001, 7, 192, 0, 12), ((1 << 20) + 3, 0, 0, 0, 15),
+         (200003, 3, 64, 0, 7)]
 
 
 @pytest.mark.parametrize("n,T,P,dc,c", SMALL)
